@@ -1,0 +1,208 @@
+/*
+ * jk_cals.h -- C ABI of the MI355X (gfx950) JK-CALS hot path.
+ *
+ * JK-CALS fits all leave-one-out jackknife submodels of a CP model at once
+ * (Psarras, Karlsson, Bro, Bientinesi, "Accelerating jackknife resampling for
+ * the Canonical Polyadic Decomposition", arXiv 2112.03985, Sec. 4.1, Alg. 3).
+ * Every submodel keeps its own factor matrices; the factors of all models
+ * are stored side by side as column blocks of one "multi-factor" per mode,
+ * and each mode's MTTKRP of all models is one fused product of the mode-n
+ * unfolding of the FULL tensor with the column-concatenated Khatri-Rao
+ * products (Alg. 3, MTTKRP step).  A submodel that leaves out sample p of
+ * the sampled mode keeps a row of zeros at index p of that mode's factor
+ * (Case II), and the fused MTTKRP's row p is discarded for that model when
+ * the sampled mode itself is updated (Case I).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Tensor T of order N (2..4) with sizes I_1..I_N: device memory, column-major
+ *   with i_1 fastest (Eq. (3)): element (i_1..i_N) at offset
+ *   i_1 + I_1*(i_2 + I_2*(i_3 + ...)).  float64 or float32 (tensor_dtype).
+ * Models: K models; model k has rank R_k (1..JKC_MAX_RANK) and leaves out
+ *   sample left_out[k] of the sampled mode (-1: full model, keeps all).
+ *   Model k owns columns [off_k, off_k + R_k) with off_k = R_0+...+R_{k-1}.
+ *   C = R_0 + ... + R_{K-1}.
+ * Factors, MTTKRP results and gradients: device float64, row-major
+ *   I_n x C (C contiguous, leading dimension C).
+ * Modes are 0-based: mode 0 is the paper's mode 1.
+ * Streams: every asynchronous call is enqueued on problem->stream (a
+ *   hipStream_t; NULL means the default stream).
+ * Memory: the library never allocates device memory.  The caller provides
+ *   one workspace of jk_cals_workspace_size() bytes (256-byte aligned) that
+ *   must outlive the context.  Inputs are copied into it at init unless
+ *   copy_tensor == 0, in which case the tensor is read in place and must
+ *   stay valid and unchanged for the life of the context.
+ * Errors: every entry point validates all arguments before it enqueues any
+ *   device work; on a non-OK status nothing has been enqueued and no state
+ *   has changed, and jk_cals_last_error() describes the problem.  A HIP
+ *   failure returns JKC_EDEVICE.  Numerical trouble inside a model (a
+ *   singular normal matrix, a non-finite value) is not an error: it is
+ *   reported per model in the status word.  Nothing is printed.
+ * Threads: a context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef JK_CALS_H
+#define JK_CALS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JKC_MAX_ORDER 4
+#define JKC_MAX_RANK 32
+
+typedef struct jkc_ctx jkc_ctx;
+
+typedef enum {
+  JKC_OK = 0,
+  JKC_EINVAL = -1,        /* an argument is invalid                         */
+  JKC_ENOMEM = -2,        /* workspace smaller than jk_cals_workspace_size  */
+  JKC_EDEVICE = -3,       /* a HIP runtime call failed                       */
+  JKC_ESTATE = -4,        /* call not valid in the context's current state  */
+  JKC_EUNSUPPORTED = -5   /* valid request this build does not provide       */
+} jkc_status;
+
+typedef enum {
+  JKC_FP64 = 0,           /* MTTKRP in float64 MFMA, float64 accumulation    */
+  JKC_SPLIT_BF16X3 = 1    /* MTTKRP as three bfloat16 MFMA products
+                             (hi*hi + hi*lo + lo*hi) with float32
+                             accumulation flushed to float64; everything
+                             else in float64                                */
+} jkc_precision;
+
+typedef enum { JKC_TENSOR_F64 = 0, JKC_TENSOR_F32 = 1 } jkc_tensor_dtype;
+
+/* Per-model status bits (jk_cals_fit / jk_cals_get_status). */
+#define JKC_ST_CONVERGED 1u   /* |fit_t - fit_{t-1}| < tol after sweep t >= 2 */
+#define JKC_ST_FALLBACK 2u    /* an update used the eigen pseudoinverse       */
+#define JKC_ST_NONFINITE 4u   /* the model's error became NaN/Inf; frozen     */
+
+typedef struct {
+  int32_t order;               /* N, 2..JKC_MAX_ORDER                         */
+  const int64_t *dims;         /* host [N], each >= 1                         */
+  int32_t sampled_mode;        /* n-hat, 0-based, in [0, N)                   */
+  int32_t num_models;          /* K >= 1                                      */
+  const int32_t *ranks;        /* host [K], 1..JKC_MAX_RANK                    */
+  const int32_t *left_out;     /* host [K], -1 or in [0, dims[sampled_mode]) */
+  int32_t tensor_dtype;        /* jkc_tensor_dtype                            */
+  int32_t precision;           /* jkc_precision                               */
+  int32_t copy_tensor;         /* 1: copy T into the workspace; 0: use in place
+                                  (FP64 precision only)                       */
+  void *stream;                /* hipStream_t, NULL = default stream          */
+} jkc_problem;
+
+/* Bytes of device workspace the problem needs.  Host only, no device work. */
+jkc_status jk_cals_workspace_size(const jkc_problem *prob, size_t *bytes);
+
+/* Create a context (Alg. 3, initialisation of the multi-factors).
+ *   tensor : device, layout above.
+ *   init   : host array [N] of device pointers; init[n] is I_n x C float64,
+ *            row-major.  Row left_out[k] of model k's block in the sampled
+ *            mode is zeroed by the library (the inserted zero row), so the
+ *            caller may pass an unzeroed parent initialisation.
+ *   workspace : device, >= jk_cals_workspace_size bytes, 256-byte aligned.
+ *   out    : receives the context.  Owned by the caller; free with
+ *            jk_cals_destroy.
+ * Enqueues the tensor copy (or bf16 hi/lo split), the slice norms
+ * ||T_{-p}||^2 used by the submodel error (Alg. 3, error step), factor
+ * packing and the initial Gram matrices.  Asynchronous on the stream. */
+jkc_status jk_cals_init(const jkc_problem *prob, const void *tensor,
+                        const double *const *init, void *workspace,
+                        size_t ws_bytes, jkc_ctx **out);
+
+/* The fused MTTKRP of Alg. 3 for one mode, at the context's current factors:
+ * out = T_(mode) (multi-factor Khatri-Rao product), with row left_out[k] of
+ * model k's columns set to 0 when mode == sampled_mode (Case I).
+ *   out : device, I_mode x C float64, row-major.  Asynchronous. */
+jkc_status jk_cals_mttkrp(jkc_ctx *ctx, int32_t mode, double *out);
+
+/* Run nsweeps full ALS sweeps (Alg. 3, one pass of the repeat loop each) for
+ * every model that is not frozen, with no convergence test (the fixed
+ * iteration protocol of Sec. 5.1).  After the last sweep, if fit != NULL,
+ * fit[k] (device [K] float64) receives 1 - ||T_{-p} - model|| / ||T_{-p}||.
+ * Asynchronous. */
+jkc_status jk_cals_sweep(jkc_ctx *ctx, int32_t nsweeps, double *fit);
+
+/* Iterate until every model has converged (|delta fit| < tol after at least
+ * two sweeps; converged models are frozen individually) or max_iters sweeps
+ * were run (Alg. 3 stopping rule; tol <= 0 disables the test).  Synchronous.
+ *   iters, status : host [K] int32 (may be NULL); fit : host [K] (may be
+ *   NULL).  status holds JKC_ST_* bits. */
+jkc_status jk_cals_fit(jkc_ctx *ctx, int32_t max_iters, double tol,
+                       int32_t *iters, double *fit, int32_t *status);
+
+/* Copy the current factor of `mode` (device I_mode x C, row-major; columns
+ * unit-norm after any sweep) and, if lambda != NULL, the column weights
+ * lambda (device [C]; the model is [[lambda; U_1..U_N]]).  Asynchronous. */
+jkc_status jk_cals_get_factors(jkc_ctx *ctx, int32_t mode, double *out,
+                               double *lambda);
+
+/* Replace the factor of `mode` (device I_mode x C) and, if lambda != NULL,
+ * lambda (device [C]); row left_out[k] of the sampled mode is re-zeroed and
+ * the mode's Gram matrices are recomputed.  Asynchronous. */
+jkc_status jk_cals_set_factors(jkc_ctx *ctx, int32_t mode, const double *in,
+                               const double *lambda);
+
+/* Per-model error e_k, fit_k (device [K] each, may be NULL) and status words
+ * and iteration counts (device [K] int32, may be NULL).  Asynchronous. */
+jkc_status jk_cals_get_status(jkc_ctx *ctx, double *err, double *fit,
+                              int32_t *status, int32_t *iters);
+
+/* Least-squares CP loss f_k = 1/2 ||T_{-p_k} - [[U^(k)]]||^2 per model for
+ * the context's factors with lambda folded into the last mode (the
+ * all-at-once formulation the paper cites in Sec. 2), and its gradient
+ * dF/dU_n = U_n H_n - M_n for every mode (an all-mode fused MTTKRP), with
+ * row left_out[k] of the sampled mode held at 0.  lambda is folded into the
+ * last factor first (and reset to 1).  loss: device [K] (may be NULL).  The
+ * gradients stay in the workspace for jk_cals_get_grad.  Asynchronous. */
+jkc_status jk_cals_loss_grad(jkc_ctx *ctx, double *loss);
+
+/* out = weights[k] * (gradient of mode `mode`) on model k's columns, from the
+ * last jk_cals_loss_grad.  weights: device [K] or NULL (all ones).
+ * out: device I_mode x C.  Asynchronous. */
+jkc_status jk_cals_get_grad(jkc_ctx *ctx, int32_t mode, const double *weights,
+                            double *out);
+
+/* Gradient refinement: fold lambda into the last factor, fix the step
+ * eta_k = 1 / sum_n ||H_n^(k)||_F from the current factors, then take
+ * `steps` steps U_n <- U_n - eta_k dF/dU_n (all modes at once).  If loss is
+ * not NULL it receives the loss at the final factors (device [K]).
+ * Asynchronous. */
+jkc_status jk_cals_refine(jkc_ctx *ctx, int32_t steps, double *loss);
+
+/* Time each candidate MTTKRP tiling of every mode on this problem and keep
+ * the fastest (restores the factors it started with).  Synchronous.
+ * Optional: a context works with its built-in choice without it. */
+jkc_status jk_cals_tune(jkc_ctx *ctx, int32_t reps);
+
+/* The current tiling of `mode` as text, e.g. "f64 wm2 wn2 tm2 tn2 bk16 s8". */
+const char *jk_cals_describe(jkc_ctx *ctx, int32_t mode);
+
+/* Number of MTTKRP tilings compiled for the context's precision (0 if ctx is
+ * NULL). */
+int32_t jk_cals_num_tilings(jkc_ctx *ctx);
+
+/* Force tiling `variant` (0 .. num_tilings-1) with `splits` K chunks
+ * (clamped to 1 .. the context's limit) for `mode`.  Any tiling gives the
+ * same result up to the order of the float64 sums.  Host only. */
+jkc_status jk_cals_set_tiling(jkc_ctx *ctx, int32_t mode, int32_t variant, int32_t splits);
+
+/* Explicit slice removal of Alg. 2: out = T with slice p of the sampled mode
+ * deleted (the reduced tensor of a plain per-submodel fit).  Shapes follow
+ * prob (dims of the full tensor); out has dims[sampled_mode]-1 in that mode,
+ * same layout rules and dtype as T.  Asynchronous on prob->stream. */
+jkc_status jk_cals_remove_slice(const jkc_problem *prob, const void *tensor,
+                                int32_t p, void *out);
+
+/* Free the host-side context (the workspace stays the caller's). */
+void jk_cals_destroy(jkc_ctx *ctx);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char *jk_cals_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JK_CALS_H */

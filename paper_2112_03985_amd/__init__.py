@@ -1,0 +1,375 @@
+"""Python binding of libjkcals (the MI355X JK-CALS hot path).
+
+Argument marshalling only: every computation runs in the HIP kernels of
+``libjkcals.so``.  The functions below carry the names of the C ABI
+(``include/jk_cals.h``) and take torch tensors for device memory; the torch
+stream current at call time is the stream the work is enqueued on.  There
+is no CPU fallback: if the shared library is missing or fails to load,
+importing the binding's functions raises.
+
+Layouts (same as the C ABI):
+* tensor: device, column-major with i_1 fastest (a flat tensor, or any
+  tensor whose memory is in that order; use :func:`to_device_tensor`);
+* factors, MTTKRP results, gradients: device float64, (I_n, C) row-major;
+* model k owns columns [off_k, off_k + ranks[k]).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libjkcals.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "jk_cals.h")
+
+JKC_OK, JKC_EINVAL, JKC_ENOMEM, JKC_EDEVICE, JKC_ESTATE, JKC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+JKC_FP64, JKC_SPLIT_BF16X3 = 0, 1
+JKC_TENSOR_F64, JKC_TENSOR_F32 = 0, 1
+JKC_ST_CONVERGED, JKC_ST_FALLBACK, JKC_ST_NONFINITE = 1, 2, 4
+MAX_RANK = 32
+
+_STATUS_NAMES = {0: "JKC_OK", -1: "JKC_EINVAL", -2: "JKC_ENOMEM", -3: "JKC_EDEVICE",
+                 -4: "JKC_ESTATE", -5: "JKC_EUNSUPPORTED"}
+
+
+class JkcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS_NAMES.get(status, str(status)), msg))
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("order", ctypes.c_int32),
+        ("dims", ctypes.POINTER(ctypes.c_int64)),
+        ("sampled_mode", ctypes.c_int32),
+        ("num_models", ctypes.c_int32),
+        ("ranks", ctypes.POINTER(ctypes.c_int32)),
+        ("left_out", ctypes.POINTER(ctypes.c_int32)),
+        ("tensor_dtype", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("copy_tensor", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libjkcals.so (in-tree).  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libjkcals.so is not built (%s); run "
+                           "`python -m paper_2112_03985_amd.build`" % LIB_PATH)
+    try:
+        import torch  # noqa: F401  (load torch's HIP runtime first: one runtime per process)
+    except Exception:
+        pass
+    L = ctypes.CDLL(LIB_PATH, mode=ctypes.RTLD_GLOBAL)
+    P, VP, I32, F64, SZ = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "jk_cals_workspace_size": (I32, [P(Problem), P(SZ)]),
+        "jk_cals_init": (I32, [P(Problem), VP, P(VP), VP, SZ, P(VP)]),
+        "jk_cals_mttkrp": (I32, [VP, I32, VP]),
+        "jk_cals_sweep": (I32, [VP, I32, VP]),
+        "jk_cals_fit": (I32, [VP, I32, F64, VP, VP, VP]),
+        "jk_cals_get_factors": (I32, [VP, I32, VP, VP]),
+        "jk_cals_set_factors": (I32, [VP, I32, VP, VP]),
+        "jk_cals_get_status": (I32, [VP, VP, VP, VP, VP]),
+        "jk_cals_loss_grad": (I32, [VP, VP]),
+        "jk_cals_get_grad": (I32, [VP, I32, VP, VP]),
+        "jk_cals_refine": (I32, [VP, I32, VP]),
+        "jk_cals_tune": (I32, [VP, I32]),
+        "jk_cals_describe": (ctypes.c_char_p, [VP, I32]),
+        "jk_cals_num_tilings": (I32, [VP]),
+        "jk_cals_set_tiling": (I32, [VP, I32, I32, I32]),
+        "jk_cals_remove_slice": (I32, [P(Problem), VP, I32, VP]),
+        "jk_cals_destroy": (None, [VP]),
+        "jk_cals_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def header_functions(path: str = HEADER) -> list:
+    """Names of the functions the C header declares."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(jk_cals_[a-z_]+)\s*\(", text)))
+
+
+def _check(st: int):
+    if st != JKC_OK:
+        raise JkcError(st, lib().jk_cals_last_error().decode())
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def to_device_tensor(T: np.ndarray, device="cuda"):
+    """Flat device copy of T in column-major (i_1 fastest) order, the
+    library's tensor layout."""
+    import torch
+    flat = np.ascontiguousarray(np.asarray(T).ravel(order="F"))
+    return torch.from_numpy(flat).to(device)
+
+
+def make_problem(dims, sampled_mode, ranks, left_out, tensor_dtype=JKC_TENSOR_F64,
+                 precision=JKC_FP64, copy_tensor=1, stream=0):
+    """Build the C problem descriptor; the returned tuple keeps the host
+    arrays alive."""
+    d = (ctypes.c_int64 * len(dims))(*[int(x) for x in dims])
+    r = (ctypes.c_int32 * len(ranks))(*[int(x) for x in ranks])
+    lo = (ctypes.c_int32 * len(left_out))(*[int(x) for x in left_out])
+    prob = Problem(len(dims), d, int(sampled_mode), len(ranks), r, lo, int(tensor_dtype),
+                   int(precision), int(copy_tensor), ctypes.c_void_p(stream))
+    return prob, (d, r, lo)
+
+
+# ---------------------------------------------------------------------------
+# Functions with the C ABI's names.
+# ---------------------------------------------------------------------------
+
+def jk_cals_workspace_size(dims, sampled_mode, ranks, left_out, tensor_dtype=JKC_TENSOR_F64,
+                           precision=JKC_FP64, copy_tensor=1) -> int:
+    prob, keep = make_problem(dims, sampled_mode, ranks, left_out, tensor_dtype, precision,
+                              copy_tensor, 0)
+    out = ctypes.c_size_t(0)
+    _check(lib().jk_cals_workspace_size(ctypes.byref(prob), ctypes.byref(out)))
+    return int(out.value)
+
+
+class JkCals:
+    """A JK-CALS context: the library context plus the torch-owned workspace
+    (and, for copy_tensor=0, the tensor) it needs to stay alive."""
+
+    def __init__(self, tensor, dims: Sequence[int], sampled_mode: int, ranks, left_out,
+                 init: Sequence, precision: int = JKC_FP64, copy_tensor: bool = True,
+                 stream=None):
+        import torch
+        self.dims = [int(x) for x in dims]
+        self.N = len(self.dims)
+        self.sampled_mode = int(sampled_mode)
+        self.ranks = np.asarray(ranks, dtype=np.int32)
+        self.left_out = np.asarray(left_out, dtype=np.int32)
+        self.K = len(self.ranks)
+        self.C = int(self.ranks.sum())
+        self.precision = int(precision)
+        if tensor.dtype == torch.float64:
+            tdt = JKC_TENSOR_F64
+        elif tensor.dtype == torch.float32:
+            tdt = JKC_TENSOR_F32
+        else:
+            raise TypeError("tensor must be float64 or float32")
+        if not tensor.is_cuda:
+            raise ValueError("tensor must be a device tensor")
+        if tensor.numel() != int(np.prod(self.dims)):
+            raise ValueError("tensor has %d elements, dims say %d" % (tensor.numel(), int(np.prod(self.dims))))
+        for n, u in enumerate(init):
+            if u.dtype != torch.float64 or not u.is_cuda or tuple(u.shape) != (self.dims[n], self.C) \
+                    or not u.is_contiguous():
+                raise ValueError("init[%d] must be a contiguous device float64 (%d, %d) tensor"
+                                 % (n, self.dims[n], self.C))
+        self.stream_handle = _stream(stream)
+        self._prob, self._keep = make_problem(self.dims, sampled_mode, self.ranks, self.left_out,
+                                              tdt, precision, 1 if copy_tensor else 0,
+                                              self.stream_handle)
+        size = ctypes.c_size_t(0)
+        _check(lib().jk_cals_workspace_size(ctypes.byref(self._prob), ctypes.byref(size)))
+        self.workspace_bytes = int(size.value)
+        self.workspace = torch.empty(max(self.workspace_bytes, 256) + 256, dtype=torch.uint8,
+                                     device=tensor.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._tensor = tensor                     # kept alive (needed when copy_tensor=0)
+        self._init = list(init)                   # kept alive until init has run
+        ptrs = (ctypes.c_void_p * self.N)(*[u.data_ptr() for u in init])
+        ctx = ctypes.c_void_p(0)
+        _check(lib().jk_cals_init(ctypes.byref(self._prob), ctypes.c_void_p(tensor.data_ptr()),
+                                  ptrs, ctypes.c_void_p(aligned),
+                                  ctypes.c_size_t(self.workspace_bytes), ctypes.byref(ctx)))
+        self.ctx = ctx
+        self.device = tensor.device
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            lib().jk_cals_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- entry points -----------------------------------------------------
+    def _out(self, rows, cols):
+        import torch
+        return torch.empty((rows, cols), dtype=torch.float64, device=self.device)
+
+    def mttkrp(self, mode: int, out=None):
+        out = self._out(self.dims[mode], self.C) if out is None else out
+        _check(lib().jk_cals_mttkrp(self.ctx, int(mode), ctypes.c_void_p(_ptr(out))))
+        return out
+
+    def sweep(self, nsweeps: int = 1, fit=None):
+        _check(lib().jk_cals_sweep(self.ctx, int(nsweeps), ctypes.c_void_p(_ptr(fit))))
+        return fit
+
+    def fit(self, max_iters: int, tol: float):
+        iters = np.zeros(self.K, np.int32)
+        fit = np.zeros(self.K, np.float64)
+        status = np.zeros(self.K, np.int32)
+        _check(lib().jk_cals_fit(self.ctx, int(max_iters), float(tol),
+                                 iters.ctypes.data_as(ctypes.c_void_p),
+                                 fit.ctypes.data_as(ctypes.c_void_p),
+                                 status.ctypes.data_as(ctypes.c_void_p)))
+        return iters, fit, status
+
+    def get_factors(self, mode: int, with_lambda: bool = True):
+        import torch
+        out = self._out(self.dims[mode], self.C)
+        lam = torch.empty(self.C, dtype=torch.float64, device=self.device) if with_lambda else None
+        _check(lib().jk_cals_get_factors(self.ctx, int(mode), ctypes.c_void_p(_ptr(out)),
+                                         ctypes.c_void_p(_ptr(lam))))
+        return (out, lam) if with_lambda else out
+
+    def set_factors(self, mode: int, U, lam=None):
+        _check(lib().jk_cals_set_factors(self.ctx, int(mode), ctypes.c_void_p(_ptr(U)),
+                                         ctypes.c_void_p(_ptr(lam))))
+
+    def get_status(self):
+        import torch
+        err = torch.empty(self.K, dtype=torch.float64, device=self.device)
+        fit = torch.empty(self.K, dtype=torch.float64, device=self.device)
+        st = torch.empty(self.K, dtype=torch.int32, device=self.device)
+        it = torch.empty(self.K, dtype=torch.int32, device=self.device)
+        _check(lib().jk_cals_get_status(self.ctx, ctypes.c_void_p(_ptr(err)), ctypes.c_void_p(_ptr(fit)),
+                                        ctypes.c_void_p(_ptr(st)), ctypes.c_void_p(_ptr(it))))
+        return err, fit, st, it
+
+    def loss_grad(self, loss=None):
+        _check(lib().jk_cals_loss_grad(self.ctx, ctypes.c_void_p(_ptr(loss))))
+        return loss
+
+    def get_grad(self, mode: int, weights=None, out=None):
+        out = self._out(self.dims[mode], self.C) if out is None else out
+        _check(lib().jk_cals_get_grad(self.ctx, int(mode), ctypes.c_void_p(_ptr(weights)),
+                                      ctypes.c_void_p(_ptr(out))))
+        return out
+
+    def refine(self, steps: int, loss=None):
+        _check(lib().jk_cals_refine(self.ctx, int(steps), ctypes.c_void_p(_ptr(loss))))
+        return loss
+
+    def tune(self, reps: int = 3):
+        _check(lib().jk_cals_tune(self.ctx, int(reps)))
+
+    def describe(self, mode: int) -> str:
+        return lib().jk_cals_describe(self.ctx, int(mode)).decode()
+
+    def num_tilings(self) -> int:
+        return int(lib().jk_cals_num_tilings(self.ctx))
+
+    def set_tiling(self, mode: int, variant: int, splits: int):
+        _check(lib().jk_cals_set_tiling(self.ctx, int(mode), int(variant), int(splits)))
+
+
+def jk_cals_init(tensor, dims, sampled_mode, ranks, left_out, init, precision=JKC_FP64,
+                 copy_tensor=True, stream=None) -> JkCals:
+    return JkCals(tensor, dims, sampled_mode, ranks, left_out, init, precision, copy_tensor, stream)
+
+
+def jk_cals_mttkrp(ctx: JkCals, mode: int, out=None):
+    return ctx.mttkrp(mode, out)
+
+
+def jk_cals_sweep(ctx: JkCals, nsweeps: int = 1, fit=None):
+    return ctx.sweep(nsweeps, fit)
+
+
+def jk_cals_fit(ctx: JkCals, max_iters: int, tol: float):
+    return ctx.fit(max_iters, tol)
+
+
+def jk_cals_get_factors(ctx: JkCals, mode: int):
+    return ctx.get_factors(mode)
+
+
+def jk_cals_set_factors(ctx: JkCals, mode: int, U, lam=None):
+    return ctx.set_factors(mode, U, lam)
+
+
+def jk_cals_get_status(ctx: JkCals):
+    return ctx.get_status()
+
+
+def jk_cals_loss_grad(ctx: JkCals, loss=None):
+    return ctx.loss_grad(loss)
+
+
+def jk_cals_get_grad(ctx: JkCals, mode: int, weights=None, out=None):
+    return ctx.get_grad(mode, weights, out)
+
+
+def jk_cals_refine(ctx: JkCals, steps: int, loss=None):
+    return ctx.refine(steps, loss)
+
+
+def jk_cals_tune(ctx: JkCals, reps: int = 3):
+    return ctx.tune(reps)
+
+
+def jk_cals_describe(ctx: JkCals, mode: int) -> str:
+    return ctx.describe(mode)
+
+
+def jk_cals_num_tilings(ctx: JkCals) -> int:
+    return ctx.num_tilings()
+
+
+def jk_cals_set_tiling(ctx: JkCals, mode: int, variant: int, splits: int):
+    return ctx.set_tiling(mode, variant, splits)
+
+
+def jk_cals_remove_slice(tensor, dims, sampled_mode, p, out=None, stream=None):
+    """Explicitly reduced tensor of Alg. 2 (slice p of the sampled mode
+    deleted), as a flat device tensor in the library layout."""
+    import torch
+    if tensor.dtype not in (torch.float64, torch.float32):
+        raise TypeError("tensor must be float64 or float32")
+    tdt = JKC_TENSOR_F64 if tensor.dtype == torch.float64 else JKC_TENSOR_F32
+    n_out = int(np.prod(dims)) // int(dims[sampled_mode]) * (int(dims[sampled_mode]) - 1)
+    if out is None:
+        out = torch.empty(n_out, dtype=tensor.dtype, device=tensor.device)
+    prob, keep = make_problem(dims, sampled_mode, [1], [-1], tdt, JKC_FP64, 1, _stream(stream))
+    _check(lib().jk_cals_remove_slice(ctypes.byref(prob), ctypes.c_void_p(tensor.data_ptr()),
+                                      int(p), ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def jk_cals_destroy(ctx: JkCals):
+    ctx.close()
+
+
+def jk_cals_last_error() -> str:
+    return lib().jk_cals_last_error().decode()

@@ -1,0 +1,825 @@
+// Host side of the JK-CALS library: argument validation, workspace layout,
+// model tables, tiling choice and tuning, and the launch sequence of the
+// concurrent ALS sweep (Alg. 3).  All device memory comes from the caller's
+// workspace; nothing here allocates on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "jkc_internal.hpp"
+
+using namespace jkc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+jkc_status fail(jkc_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define JKC_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(JKC_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+#define JKC_TRY(expr)                  \
+  do {                                 \
+    jkc_status s_ = (expr);            \
+    if (s_ != JKC_OK) return s_;       \
+  } while (0)
+
+constexpr int64_t kAlign = 256;
+constexpr int kNumCU = 256;
+constexpr int kSliceChunks = 256;
+
+int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Sizes derived from a validated problem, shared by the size query and init.
+struct Plan {
+  int N = 0, nhat = 0, K = 0, C = 0, ldc = 0;
+  int64_t dims[kMaxOrder] = {0, 0, 0, 0};
+  int64_t strides[kMaxOrder] = {0, 0, 0, 0};
+  int64_t P = 0, maxI = 0, gsize = 0;
+  int tensor_f32 = 0, precision = 0, copy_tensor = 1;
+  int split_max[kMaxOrder] = {1, 1, 1, 1};
+  int64_t partial_doubles = 0;
+
+  struct Item {
+    const char* name;
+    int64_t bytes;
+  };
+  std::vector<Item> items;
+  int64_t total = 0;
+
+  void layout() {
+    items.clear();
+    const int64_t es = tensor_f32 ? 4 : 8;
+    int64_t tbytes = 0;
+    if (precision == JKC_SPLIT_BF16X3)
+      tbytes = 2 * P * 2;
+    else if (copy_tensor)
+      tbytes = P * es;
+    items.push_back({"tensor", tbytes});
+    for (int n = 0; n < N; ++n) items.push_back({"U", dims[n] * ldc * 8});
+    for (int n = 0; n < N; ++n) items.push_back({"G", gsize * 8});
+    for (int n = 0; n < N; ++n) items.push_back({"grad", dims[n] * ldc * 8});
+    items.push_back({"M", maxI * ldc * 8});
+    items.push_back({"partial", partial_doubles * 8});
+    items.push_back({"lambda", (int64_t)ldc * 8});
+    items.push_back({"normT2", (int64_t)K * 8});
+    items.push_back({"err", (int64_t)K * 8});
+    items.push_back({"fit", (int64_t)K * 8});
+    items.push_back({"fit_prev", (int64_t)K * 8});
+    items.push_back({"eta", (int64_t)K * 8});
+    items.push_back({"status", (int64_t)K * 4});
+    items.push_back({"iters", (int64_t)K * 4});
+    items.push_back({"off", (int64_t)K * 4});
+    items.push_back({"rank", (int64_t)K * 4});
+    items.push_back({"left", (int64_t)K * 4});
+    items.push_back({"order", (int64_t)K * 4});
+    items.push_back({"goff", (int64_t)K * 8});
+    items.push_back({"colp", (int64_t)ldc * 4});
+    items.push_back({"colmodel", (int64_t)ldc * 4});
+    items.push_back({"slice", dims[nhat] * 8});
+    items.push_back({"slice_part", (int64_t)kSliceChunks * dims[nhat] * 8});
+    items.push_back({"counter", 4});
+    total = 0;
+    for (auto& it : items) total += align_up(std::max<int64_t>(it.bytes, 1), kAlign);
+  }
+};
+
+// Upper bound on split-K chunks for a mode: enough to fill the chip when the
+// output is small, none when the output alone is large (its own tiles fill
+// the chip), and partials bounded to 64 MB or four output planes.
+int split_cap(int64_t rows, int64_t ldc, int64_t J) {
+  const int64_t plane = rows * ldc * 8;
+  const int64_t budget = std::max<int64_t>(64ll << 20, 4 * plane);
+  int64_t s = budget / std::max<int64_t>(plane, 1);
+  s = std::min<int64_t>(s, 64);
+  s = std::min<int64_t>(s, std::max<int64_t>(1, J / 64));
+  return (int)std::max<int64_t>(s, 1);
+}
+
+jkc_status make_plan(const jkc_problem* prob, Plan* pl) {
+  if (!prob) return fail(JKC_EINVAL, "problem is NULL");
+  if (prob->order < 2 || prob->order > kMaxOrder)
+    return fail(JKC_EINVAL, "order must be in 2..4");
+  if (!prob->dims) return fail(JKC_EINVAL, "dims is NULL");
+  pl->N = prob->order;
+  int64_t P = 1;
+  for (int n = 0; n < pl->N; ++n) {
+    const int64_t d = prob->dims[n];
+    if (d < 1 || d > (1ll << 30)) return fail(JKC_EINVAL, "dims must be in 1..2^30");
+    pl->dims[n] = d;
+    pl->strides[n] = P;
+    P *= d;
+    if (P > (1ll << 40)) return fail(JKC_EINVAL, "tensor larger than 2^40 elements");
+  }
+  pl->P = P;
+  for (int n = 0; n < pl->N; ++n)
+    if (P / pl->dims[n] >= (1ll << 31))
+      return fail(JKC_EINVAL, "an unfolding has 2^31 or more columns");
+  if (prob->sampled_mode < 0 || prob->sampled_mode >= pl->N)
+    return fail(JKC_EINVAL, "sampled_mode out of range");
+  pl->nhat = prob->sampled_mode;
+  if (prob->num_models < 1) return fail(JKC_EINVAL, "num_models must be >= 1");
+  if (!prob->ranks || !prob->left_out) return fail(JKC_EINVAL, "ranks/left_out is NULL");
+  pl->K = prob->num_models;
+  int64_t C = 0, gsize = 0;
+  const int64_t Ih = pl->dims[pl->nhat];
+  for (int k = 0; k < pl->K; ++k) {
+    const int R = prob->ranks[k];
+    if (R < 1 || R > kMaxRank) return fail(JKC_EINVAL, "rank must be in 1..32 (model " + std::to_string(k) + ")");
+    const int p = prob->left_out[k];
+    if (p < -1 || p >= Ih) return fail(JKC_EINVAL, "left_out out of range (model " + std::to_string(k) + ")");
+    if (p >= 0 && Ih < 2) return fail(JKC_EINVAL, "cannot leave out the only sample");
+    C += R;
+    gsize += (int64_t)R * R;
+  }
+  if (C > (1ll << 28)) return fail(JKC_EINVAL, "too many columns");
+  pl->C = (int)C;
+  pl->ldc = (int)align_up(C, kColAlign);
+  pl->gsize = gsize;
+  if (prob->tensor_dtype != JKC_TENSOR_F64 && prob->tensor_dtype != JKC_TENSOR_F32)
+    return fail(JKC_EINVAL, "tensor_dtype must be 0 (f64) or 1 (f32)");
+  pl->tensor_f32 = prob->tensor_dtype == JKC_TENSOR_F32;
+  if (prob->precision != JKC_FP64 && prob->precision != JKC_SPLIT_BF16X3)
+    return fail(JKC_EINVAL, "precision must be 0 (fp64) or 1 (split bf16x3)");
+  pl->precision = prob->precision;
+  if (prob->copy_tensor != 0 && prob->copy_tensor != 1)
+    return fail(JKC_EINVAL, "copy_tensor must be 0 or 1");
+  pl->copy_tensor = prob->copy_tensor;
+  if (!pl->copy_tensor && pl->precision != JKC_FP64)
+    return fail(JKC_EINVAL, "copy_tensor = 0 needs precision JKC_FP64");
+  pl->maxI = 0;
+  pl->partial_doubles = 0;
+  for (int n = 0; n < pl->N; ++n) {
+    pl->maxI = std::max(pl->maxI, pl->dims[n]);
+    const int64_t J = P / pl->dims[n];
+    pl->split_max[n] = split_cap(pl->dims[n], pl->ldc, J);
+    if (pl->split_max[n] > 1)
+      pl->partial_doubles =
+          std::max(pl->partial_doubles, (int64_t)pl->split_max[n] * pl->dims[n] * pl->ldc);
+  }
+  pl->layout();
+  return JKC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tiling choice.
+// ---------------------------------------------------------------------------
+struct ModeShape {
+  int64_t M, J;
+  int ncols, ldc, split_max;
+};
+
+Tiling make_tiling(const std::vector<MttkrpVariant>& vars, int v, const ModeShape& s, int splits) {
+  Tiling t;
+  const auto& x = vars[v];
+  t.variant = v;
+  t.wm = x.wm; t.wn = x.wn; t.tm = x.tm; t.tn = x.tn; t.bk = x.bk;
+  t.splits = std::max(1, std::min(splits, s.split_max));
+  return t;
+}
+
+int default_splits(const Tiling& t, const ModeShape& s) {
+  const int64_t tiles = ((s.M + t.bm() - 1) / t.bm()) * ((s.ncols + t.bn() - 1) / t.bn());
+  const int waves_per_block = t.wm * t.wn;
+  // aim for about two resident waves per SIMD: 2 * 4 * 256 waves
+  const int64_t want_blocks = (2 * 4 * kNumCU) / waves_per_block;
+  int64_t s_ = (want_blocks + tiles - 1) / tiles;
+  s_ = std::min<int64_t>(s_, std::max<int64_t>(1, s.J / (4 * t.bk)));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(s_, s.split_max));
+}
+
+double model_cost(const Tiling& t, const ModeShape& s) {
+  const int64_t mt = (s.M + t.bm() - 1) / t.bm();
+  const int64_t nt = (s.ncols + t.bn() - 1) / t.bn();
+  const double padded = (double)mt * t.bm() * nt * t.bn() * (double)s.J;
+  const double waves = (double)mt * nt * t.splits * t.wm * t.wn;
+  const double fill = std::min(1.0, waves / (4.0 * kNumCU));
+  // MFMA time at 128 flop/clk/CU (float64), in arbitrary units
+  double cost = 2.0 * padded / fill;
+  // split-K partial traffic, written and read once (~64 flops per byte)
+  if (t.splits > 1) cost += 64.0 * 2.0 * 8.0 * t.splits * (double)s.M * s.ldc;
+  // re-reads of the tensor per column tile
+  cost += 64.0 * 8.0 * (double)s.M * s.J * nt * 0.25;
+  return cost;
+}
+
+Tiling choose_tiling(const std::vector<MttkrpVariant>& vars, const ModeShape& s) {
+  Tiling best;
+  double best_cost = std::numeric_limits<double>::infinity();
+  for (int v = 0; v < (int)vars.size(); ++v) {
+    Tiling t = make_tiling(vars, v, s, 1);
+    t.splits = default_splits(t, s);
+    const double c = model_cost(t, s);
+    if (c < best_cost) {
+      best_cost = c;
+      best = t;
+    }
+  }
+  return best;
+}
+
+ModeShape mode_shape(const jkc_ctx* ctx, int n, int split_max) {
+  ModeShape s;
+  s.M = ctx->dims[n];
+  s.J = ctx->P / ctx->dims[n];
+  s.ncols = ctx->C;
+  s.ldc = ctx->ldc;
+  s.split_max = split_max;
+  return s;
+}
+
+std::string describe_tiling(const Tiling& t, int precision) {
+  char buf[128];
+  snprintf(buf, sizeof(buf), "%s wm%d wn%d tm%d tn%d bk%d s%d", precision ? "bf16x3" : "f64", t.wm,
+           t.wn, t.tm, t.tn, t.bk, t.splits);
+  return buf;
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers.
+// ---------------------------------------------------------------------------
+const std::vector<MttkrpVariant>& variants_for(const jkc_ctx* ctx) {
+  return ctx->precision == JKC_SPLIT_BF16X3 ? mttkrp_split_variants() : mttkrp_f64_variants();
+}
+
+// Enqueue the fused MTTKRP of mode n.  Result: split-K partials in
+// ctx->partial (t.splits > 1) or the product itself in ctx->Mbuf.
+jkc_status enqueue_mttkrp(jkc_ctx* ctx, int n, const Tiling& t) {
+  const auto& vars = variants_for(ctx);
+  if (t.variant < 0 || t.variant >= (int)vars.size()) return fail(JKC_ESTATE, "no tiling");
+  MttkrpArgs a{};
+  if (ctx->precision == JKC_SPLIT_BF16X3) {
+    a.T = ctx->T_hi;
+    a.T_lo = ctx->T_lo;
+  } else {
+    a.T = ctx->T;
+    a.T_lo = nullptr;
+  }
+  a.t_is_f32 = ctx->tensor_f32;
+  int q = 0;
+  for (int m = 0; m < ctx->N; ++m) {
+    if (m == n) continue;
+    a.oU[q] = ctx->U[m];
+    a.odim[q] = (int32_t)ctx->dims[m];
+    a.ostride[q] = ctx->strides[m];
+    ++q;
+  }
+  for (; q < kMaxOrder - 1; ++q) {
+    a.oU[q] = nullptr;
+    a.odim[q] = 1;
+    a.ostride[q] = 0;
+  }
+  a.nother = ctx->N - 1;
+  a.stride_n = ctx->strides[n];
+  a.M = (int32_t)ctx->dims[n];
+  a.J = ctx->P / ctx->dims[n];
+  a.ldc = ctx->ldc;
+  a.ncols = ctx->C;
+  a.mtiles = (int32_t)((a.M + t.bm() - 1) / t.bm());
+  a.ntiles = (int32_t)((a.ncols + t.bn() - 1) / t.bn());
+  int64_t kchunk = (a.J + t.splits - 1) / t.splits;
+  kchunk = align_up(kchunk, t.bk);
+  const int splits = (int)((a.J + kchunk - 1) / kchunk);
+  a.kchunk = kchunk;
+  a.splits = splits;
+  if (splits > 1) {
+    if ((int64_t)splits * a.M * a.ldc > ctx->partial_doubles)
+      return fail(JKC_ESTATE, "split-K partial buffer too small");
+    a.partial = ctx->partial;
+  } else {
+    a.partial = ctx->Mbuf;
+  }
+  JKC_HIP(vars[t.variant].launch(a, ctx->stream));
+  return JKC_OK;
+}
+
+int effective_splits(const jkc_ctx* ctx, int n, const Tiling& t) {
+  const int64_t J = ctx->P / ctx->dims[n];
+  int64_t kchunk = align_up((J + t.splits - 1) / t.splits, t.bk);
+  return (int)((J + kchunk - 1) / kchunk);
+}
+
+// MTTKRP of mode n reduced into out (ld ldo, ncols columns), with the Case I
+// row removal when n is the sampled mode.
+jkc_status enqueue_mttkrp_reduced(jkc_ctx* ctx, int n, double* out, int ldo, int ncols) {
+  const Tiling& t = ctx->tiling[n];
+  JKC_TRY(enqueue_mttkrp(ctx, n, t));
+  const int splits = effective_splits(ctx, n, t);
+  const double* src = splits > 1 ? ctx->partial : ctx->Mbuf;
+  if (splits == 1 && out == ctx->Mbuf) return JKC_OK;  // rows cleared by the consumer
+  JKC_HIP(launch_reduce(src, splits, (int32_t)ctx->dims[n], ctx->ldc, ncols, ctx->d_colp,
+                        n == ctx->nhat ? 1 : 0, out, ldo, ctx->stream));
+  return JKC_OK;
+}
+
+jkc_status enqueue_update(jkc_ctx* ctx, int n, double tol, int check_conv) {
+  JKC_TRY(enqueue_mttkrp_reduced(ctx, n, ctx->Mbuf, ctx->ldc, ctx->ldc));
+  UpdateArgs a{};
+  a.mt = ctx->table();
+  a.N = ctx->N;
+  a.n = n;
+  a.nhat = ctx->nhat;
+  a.In = (int32_t)ctx->dims[n];
+  a.ldc = ctx->ldc;
+  a.partial = nullptr;
+  a.splits = 1;
+  a.Mout = ctx->Mbuf;
+  a.U = ctx->U[n];
+  for (int m = 0; m < kMaxOrder; ++m) a.G[m] = ctx->G[m];
+  a.lambda = ctx->lambda;
+  a.normT2 = ctx->normT2;
+  a.err = ctx->err;
+  a.fit = ctx->fit;
+  a.fit_prev = ctx->fit_prev;
+  a.status = ctx->status;
+  a.iters = ctx->iters;
+  a.last_mode = (n == ctx->N - 1) ? 1 : 0;
+  a.tol = tol;
+  a.check_conv = check_conv;
+  JKC_HIP(launch_update(a, ctx->stream));
+  return JKC_OK;
+}
+
+jkc_status enqueue_sweeps(jkc_ctx* ctx, int nsweeps, double tol, int check_conv) {
+  for (int s = 0; s < nsweeps; ++s)
+    for (int n = 0; n < ctx->N; ++n) JKC_TRY(enqueue_update(ctx, n, tol, check_conv));
+  if (nsweeps > 0) ctx->lambda_is_one = false;
+  return JKC_OK;
+}
+
+jkc_status enqueue_gram(jkc_ctx* ctx, int n) {
+  GramArgs g{};
+  g.mt = ctx->table();
+  g.rows = (int32_t)ctx->dims[n];
+  g.ldc = ctx->ldc;
+  g.U = ctx->U[n];
+  g.G = ctx->G[n];
+  JKC_HIP(launch_gram(g, ctx->stream));
+  return JKC_OK;
+}
+
+jkc_status enqueue_fold_lambda(jkc_ctx* ctx) {
+  if (ctx->lambda_is_one) return JKC_OK;
+  const int n = ctx->N - 1;
+  JKC_HIP(launch_fold_lambda(ctx->U[n], (int32_t)ctx->dims[n], ctx->ldc, ctx->C, ctx->lambda,
+                             ctx->stream));
+  JKC_TRY(enqueue_gram(ctx, n));
+  ctx->lambda_is_one = true;
+  return JKC_OK;
+}
+
+// All-mode gradient at the current factors (lambda folded), loss optional.
+jkc_status enqueue_loss_grad(jkc_ctx* ctx, double* loss) {
+  JKC_TRY(enqueue_fold_lambda(ctx));
+  for (int n = 0; n < ctx->N; ++n) {
+    JKC_TRY(enqueue_mttkrp_reduced(ctx, n, ctx->Mbuf, ctx->ldc, ctx->ldc));
+    if (effective_splits(ctx, n, ctx->tiling[n]) == 1 && n == ctx->nhat) {
+      // the direct product still carries row p: clear it through a reduce pass
+      JKC_HIP(launch_reduce(ctx->Mbuf, 1, (int32_t)ctx->dims[n], ctx->ldc, ctx->ldc, ctx->d_colp,
+                            1, ctx->Mbuf, ctx->ldc, ctx->stream));
+    }
+    GradArgs g{};
+    g.mt = ctx->table();
+    g.N = ctx->N;
+    g.n = n;
+    g.nhat = ctx->nhat;
+    g.In = (int32_t)ctx->dims[n];
+    g.ldc = ctx->ldc;
+    g.Mfull = ctx->Mbuf;
+    g.U = ctx->U[n];
+    for (int m = 0; m < kMaxOrder; ++m) g.Gp[m] = ctx->G[m];
+    g.grad = ctx->grad[n];
+    g.normT2 = ctx->normT2;
+    g.loss = loss;
+    g.last_mode = (loss != nullptr && n == ctx->N - 1) ? 1 : 0;
+    JKC_HIP(launch_grad_assemble(g, ctx->stream));
+  }
+  return JKC_OK;
+}
+
+jkc_status check_ctx(const jkc_ctx* ctx) {
+  if (!ctx) return fail(JKC_EINVAL, "context is NULL");
+  return JKC_OK;
+}
+
+jkc_status check_mode(const jkc_ctx* ctx, int mode) {
+  if (mode < 0 || mode >= ctx->N) return fail(JKC_EINVAL, "mode out of range");
+  return JKC_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Exported C ABI.
+// ===========================================================================
+extern "C" {
+
+const char* jk_cals_last_error(void) { return g_last_error.c_str(); }
+
+jkc_status jk_cals_workspace_size(const jkc_problem* prob, size_t* bytes) {
+  if (!bytes) return fail(JKC_EINVAL, "bytes is NULL");
+  Plan pl;
+  JKC_TRY(make_plan(prob, &pl));
+  *bytes = (size_t)pl.total;
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const double* const* init,
+                        void* workspace, size_t ws_bytes, jkc_ctx** out) {
+  if (!out) return fail(JKC_EINVAL, "out is NULL");
+  *out = nullptr;
+  Plan pl;
+  JKC_TRY(make_plan(prob, &pl));
+  if (!tensor) return fail(JKC_EINVAL, "tensor is NULL");
+  if (!init) return fail(JKC_EINVAL, "init is NULL");
+  for (int n = 0; n < pl.N; ++n)
+    if (!init[n]) return fail(JKC_EINVAL, "init[" + std::to_string(n) + "] is NULL");
+  if (!workspace) return fail(JKC_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(JKC_EINVAL, "workspace must be 256-byte aligned");
+  if ((int64_t)ws_bytes < pl.total)
+    return fail(JKC_ENOMEM, "workspace too small: need " + std::to_string(pl.total) + " bytes");
+
+  std::unique_ptr<jkc_ctx> ctx(new (std::nothrow) jkc_ctx());
+  if (!ctx) return fail(JKC_ENOMEM, "host allocation failed");
+  jkc_ctx& c = *ctx;
+  c.N = pl.N;
+  c.nhat = pl.nhat;
+  c.K = pl.K;
+  c.C = pl.C;
+  c.ldc = pl.ldc;
+  c.P = pl.P;
+  for (int n = 0; n < kMaxOrder; ++n) {
+    c.dims[n] = pl.dims[n];
+    c.strides[n] = pl.strides[n];
+  }
+  c.tensor_f32 = pl.tensor_f32;
+  c.precision = pl.precision;
+  c.stream = static_cast<hipStream_t>(prob->stream);
+  c.gsize = pl.gsize;
+  c.partial_doubles = pl.partial_doubles;
+  c.h_rank.assign(prob->ranks, prob->ranks + pl.K);
+  c.h_left.assign(prob->left_out, prob->left_out + pl.K);
+  c.h_off.resize(pl.K);
+  c.h_goff.resize(pl.K);
+  c.h_colp.assign(pl.ldc, -1);
+  c.h_colmodel.assign(pl.ldc, 0);
+  int32_t off = 0;
+  int64_t goff = 0;
+  for (int k = 0; k < pl.K; ++k) {
+    c.h_off[k] = off;
+    c.h_goff[k] = goff;
+    for (int r = 0; r < c.h_rank[k]; ++r) {
+      c.h_colp[off + r] = c.h_left[k];
+      c.h_colmodel[off + r] = k;
+    }
+    off += c.h_rank[k];
+    goff += (int64_t)c.h_rank[k] * c.h_rank[k];
+  }
+  // most expensive models first (rank^2 work per row), stable by index
+  c.h_order.resize(pl.K);
+  std::iota(c.h_order.begin(), c.h_order.end(), 0);
+  std::stable_sort(c.h_order.begin(), c.h_order.end(),
+                   [&](int a, int b) { return c.h_rank[a] > c.h_rank[b]; });
+
+  // carve the workspace
+  char* base = static_cast<char*>(workspace);
+  int64_t pos = 0;
+  auto take = [&](size_t idx) -> void* {
+    void* p = base + pos;
+    pos += align_up(std::max<int64_t>(pl.items[idx].bytes, 1), kAlign);
+    return p;
+  };
+  size_t it = 0;
+  void* tbuf = take(it++);
+  for (int n = 0; n < pl.N; ++n) c.U[n] = static_cast<double*>(take(it++));
+  for (int n = 0; n < pl.N; ++n) c.G[n] = static_cast<double*>(take(it++));
+  for (int n = 0; n < pl.N; ++n) c.grad[n] = static_cast<double*>(take(it++));
+  c.Mbuf = static_cast<double*>(take(it++));
+  c.partial = static_cast<double*>(take(it++));
+  c.lambda = static_cast<double*>(take(it++));
+  c.normT2 = static_cast<double*>(take(it++));
+  c.err = static_cast<double*>(take(it++));
+  c.fit = static_cast<double*>(take(it++));
+  c.fit_prev = static_cast<double*>(take(it++));
+  c.eta = static_cast<double*>(take(it++));
+  c.status = static_cast<int32_t*>(take(it++));
+  c.iters = static_cast<int32_t*>(take(it++));
+  c.d_off = static_cast<int32_t*>(take(it++));
+  c.d_rank = static_cast<int32_t*>(take(it++));
+  c.d_left = static_cast<int32_t*>(take(it++));
+  c.d_order = static_cast<int32_t*>(take(it++));
+  c.d_goff = static_cast<int64_t*>(take(it++));
+  c.d_colp = static_cast<int32_t*>(take(it++));
+  c.d_colmodel = static_cast<int32_t*>(take(it++));
+  c.slice = static_cast<double*>(take(it++));
+  c.slice_part = static_cast<double*>(take(it++));
+  c.counter = static_cast<int32_t*>(take(it++));
+
+  hipStream_t st = c.stream;
+  // model tables (host vectors live in the context, so the copies are safe)
+  JKC_HIP(hipMemcpyAsync(c.d_off, c.h_off.data(), pl.K * 4, hipMemcpyHostToDevice, st));
+  JKC_HIP(hipMemcpyAsync(c.d_rank, c.h_rank.data(), pl.K * 4, hipMemcpyHostToDevice, st));
+  JKC_HIP(hipMemcpyAsync(c.d_left, c.h_left.data(), pl.K * 4, hipMemcpyHostToDevice, st));
+  JKC_HIP(hipMemcpyAsync(c.d_order, c.h_order.data(), pl.K * 4, hipMemcpyHostToDevice, st));
+  JKC_HIP(hipMemcpyAsync(c.d_goff, c.h_goff.data(), pl.K * 8, hipMemcpyHostToDevice, st));
+  JKC_HIP(hipMemcpyAsync(c.d_colp, c.h_colp.data(), pl.ldc * 4, hipMemcpyHostToDevice, st));
+  JKC_HIP(hipMemcpyAsync(c.d_colmodel, c.h_colmodel.data(), pl.ldc * 4, hipMemcpyHostToDevice, st));
+
+  // tensor residency
+  if (pl.precision == JKC_SPLIT_BF16X3) {
+    c.T_hi = static_cast<uint16_t*>(tbuf);
+    c.T_lo = c.T_hi + pl.P;
+    JKC_HIP(launch_split_tensor(tensor, pl.tensor_f32, c.T_hi, c.T_lo, pl.P, st));
+  } else if (pl.copy_tensor) {
+    JKC_HIP(launch_copy_tensor(tensor, pl.tensor_f32, tbuf, pl.P, st));
+    c.T = tbuf;
+  } else {
+    c.T = tensor;
+  }
+  // slice norms of the sampled mode, from the caller's tensor (exact values)
+  {
+    const int64_t I = pl.dims[pl.nhat];
+    const int64_t inner = pl.strides[pl.nhat];
+    const int64_t outer = pl.P / (inner * I);
+    const int chunks = (int)std::min<int64_t>(kSliceChunks, outer);
+    JKC_HIP(launch_slice_norms(tensor, pl.tensor_f32, inner, (int32_t)I, outer, c.slice_part,
+                               chunks, c.slice, st));
+    JKC_HIP(launch_model_norms(c.slice, (int32_t)I, c.d_left, pl.K, c.normT2, st));
+  }
+  // multi-factors with the inserted zero rows, then Grams
+  for (int n = 0; n < pl.N; ++n) {
+    JKC_HIP(launch_pack_factor(init[n], pl.C, (int32_t)pl.dims[n], pl.C, pl.ldc, c.d_colp,
+                               n == pl.nhat ? 1 : 0, c.U[n], st));
+  }
+  for (int n = 0; n < pl.N; ++n) JKC_TRY(enqueue_gram(&c, n));
+  JKC_HIP(launch_fill(c.lambda, pl.ldc, 1.0, st));
+  JKC_HIP(launch_fill(c.err, pl.K, 0.0, st));
+  JKC_HIP(launch_fill(c.fit, pl.K, 0.0, st));
+  JKC_HIP(launch_fill(c.fit_prev, pl.K, 0.0, st));
+  JKC_HIP(launch_fill_i32(c.status, pl.K, 0, st));
+  JKC_HIP(launch_fill_i32(c.iters, pl.K, 0, st));
+  c.lambda_is_one = true;
+
+  // tilings
+  const auto& vars = variants_for(&c);
+  if (vars.empty()) return fail(JKC_EUNSUPPORTED, "no MTTKRP kernels for this precision");
+  for (int n = 0; n < pl.N; ++n) {
+    c.split_max[n] = pl.split_max[n];
+    c.tiling[n] = choose_tiling(vars, mode_shape(&c, n, pl.split_max[n]));
+    c.describe[n] = describe_tiling(c.tiling[n], c.precision);
+  }
+  *out = ctx.release();
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+void jk_cals_destroy(jkc_ctx* ctx) { delete ctx; }
+
+jkc_status jk_cals_mttkrp(jkc_ctx* ctx, int32_t mode, double* out) {
+  JKC_TRY(check_ctx(ctx));
+  JKC_TRY(check_mode(ctx, mode));
+  if (!out) return fail(JKC_EINVAL, "out is NULL");
+  const Tiling& t = ctx->tiling[mode];
+  JKC_TRY(enqueue_mttkrp(ctx, mode, t));
+  const int splits = effective_splits(ctx, mode, t);
+  JKC_HIP(launch_reduce(splits > 1 ? ctx->partial : ctx->Mbuf, splits, (int32_t)ctx->dims[mode],
+                        ctx->ldc, ctx->C, ctx->d_colp, mode == ctx->nhat ? 1 : 0, out, ctx->C,
+                        ctx->stream));
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_sweep(jkc_ctx* ctx, int32_t nsweeps, double* fit) {
+  JKC_TRY(check_ctx(ctx));
+  if (nsweeps < 0) return fail(JKC_EINVAL, "nsweeps must be >= 0");
+  JKC_TRY(enqueue_sweeps(ctx, nsweeps, 0.0, 0));
+  if (fit)
+    JKC_HIP(hipMemcpyAsync(fit, ctx->fit, ctx->K * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_fit(jkc_ctx* ctx, int32_t max_iters, double tol, int32_t* iters, double* fit,
+                       int32_t* status) {
+  JKC_TRY(check_ctx(ctx));
+  if (max_iters < 0) return fail(JKC_EINVAL, "max_iters must be >= 0");
+  const int check_every = 5;
+  const int conv = tol > 0.0 ? 1 : 0;
+  for (int t = 0; t < max_iters; ++t) {
+    for (int n = 0; n < ctx->N; ++n) JKC_TRY(enqueue_update(ctx, n, tol, conv));
+    ctx->lambda_is_one = false;
+    if (conv && ((t + 1) % check_every == 0 || t + 1 == max_iters)) {
+      int32_t active = 0;
+      JKC_HIP(launch_count_active(ctx->status, ctx->K, ctx->counter, ctx->stream));
+      JKC_HIP(hipMemcpyAsync(&active, ctx->counter, 4, hipMemcpyDeviceToHost, ctx->stream));
+      JKC_HIP(hipStreamSynchronize(ctx->stream));
+      if (active == 0) break;
+    }
+  }
+  if (iters) JKC_HIP(hipMemcpyAsync(iters, ctx->iters, ctx->K * 4, hipMemcpyDeviceToHost, ctx->stream));
+  if (fit) JKC_HIP(hipMemcpyAsync(fit, ctx->fit, ctx->K * 8, hipMemcpyDeviceToHost, ctx->stream));
+  if (status)
+    JKC_HIP(hipMemcpyAsync(status, ctx->status, ctx->K * 4, hipMemcpyDeviceToHost, ctx->stream));
+  JKC_HIP(hipStreamSynchronize(ctx->stream));
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_get_factors(jkc_ctx* ctx, int32_t mode, double* out, double* lambda) {
+  JKC_TRY(check_ctx(ctx));
+  JKC_TRY(check_mode(ctx, mode));
+  if (!out) return fail(JKC_EINVAL, "out is NULL");
+  JKC_HIP(launch_unpack(ctx->U[mode], ctx->ldc, (int32_t)ctx->dims[mode], ctx->C, out, ctx->stream));
+  if (lambda)
+    JKC_HIP(hipMemcpyAsync(lambda, ctx->lambda, ctx->C * 8, hipMemcpyDeviceToDevice, ctx->stream));
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_set_factors(jkc_ctx* ctx, int32_t mode, const double* in, const double* lambda) {
+  JKC_TRY(check_ctx(ctx));
+  JKC_TRY(check_mode(ctx, mode));
+  if (!in) return fail(JKC_EINVAL, "in is NULL");
+  JKC_HIP(launch_pack_factor(in, ctx->C, (int32_t)ctx->dims[mode], ctx->C, ctx->ldc, ctx->d_colp,
+                             mode == ctx->nhat ? 1 : 0, ctx->U[mode], ctx->stream));
+  JKC_TRY(enqueue_gram(ctx, mode));
+  if (lambda) {
+    JKC_HIP(hipMemcpyAsync(ctx->lambda, lambda, ctx->C * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->lambda_is_one = false;
+  }
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_get_status(jkc_ctx* ctx, double* err, double* fit, int32_t* status,
+                              int32_t* iters) {
+  JKC_TRY(check_ctx(ctx));
+  hipStream_t s = ctx->stream;
+  if (err) JKC_HIP(hipMemcpyAsync(err, ctx->err, ctx->K * 8, hipMemcpyDeviceToDevice, s));
+  if (fit) JKC_HIP(hipMemcpyAsync(fit, ctx->fit, ctx->K * 8, hipMemcpyDeviceToDevice, s));
+  if (status) JKC_HIP(hipMemcpyAsync(status, ctx->status, ctx->K * 4, hipMemcpyDeviceToDevice, s));
+  if (iters) JKC_HIP(hipMemcpyAsync(iters, ctx->iters, ctx->K * 4, hipMemcpyDeviceToDevice, s));
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_loss_grad(jkc_ctx* ctx, double* loss) {
+  JKC_TRY(check_ctx(ctx));
+  JKC_TRY(enqueue_loss_grad(ctx, loss));
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_get_grad(jkc_ctx* ctx, int32_t mode, const double* weights, double* out) {
+  JKC_TRY(check_ctx(ctx));
+  JKC_TRY(check_mode(ctx, mode));
+  if (!out) return fail(JKC_EINVAL, "out is NULL");
+  JKC_HIP(launch_scale_cols_by_model(ctx->table(), weights, ctx->grad[mode],
+                                     (int32_t)ctx->dims[mode], ctx->ldc, out, ctx->C, ctx->C,
+                                     ctx->stream));
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_refine(jkc_ctx* ctx, int32_t steps, double* loss) {
+  JKC_TRY(check_ctx(ctx));
+  if (steps < 0) return fail(JKC_EINVAL, "steps must be >= 0");
+  JKC_TRY(enqueue_fold_lambda(ctx));
+  const double* G[kMaxOrder] = {ctx->G[0], ctx->G[1], ctx->G[2], ctx->G[3]};
+  JKC_HIP(launch_gd_eta(ctx->table(), ctx->N, G, ctx->eta, ctx->stream));
+  for (int s = 0; s < steps; ++s) {
+    JKC_TRY(enqueue_loss_grad(ctx, nullptr));
+    for (int n = 0; n < ctx->N; ++n)
+      JKC_HIP(launch_gd_step(ctx->table(), ctx->eta, ctx->d_colmodel, ctx->U[n], ctx->grad[n],
+                             (int32_t)ctx->dims[n], ctx->ldc, ctx->C, ctx->stream));
+    for (int n = 0; n < ctx->N; ++n) JKC_TRY(enqueue_gram(ctx, n));
+  }
+  if (loss) JKC_TRY(enqueue_loss_grad(ctx, loss));
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_tune(jkc_ctx* ctx, int32_t reps) {
+  JKC_TRY(check_ctx(ctx));
+  if (reps < 1) return fail(JKC_EINVAL, "reps must be >= 1");
+  const auto& vars = variants_for(ctx);
+  hipEvent_t e0, e1;
+  JKC_HIP(hipEventCreate(&e0));
+  JKC_HIP(hipEventCreate(&e1));
+  jkc_status result = JKC_OK;
+  for (int n = 0; n < ctx->N && result == JKC_OK; ++n) {
+    const ModeShape shape = mode_shape(ctx, n, ctx->split_max[n]);
+    Tiling best = ctx->tiling[n];
+    float best_ms = std::numeric_limits<float>::infinity();
+    for (int v = 0; v < (int)vars.size() && result == JKC_OK; ++v) {
+      Tiling base = make_tiling(vars, v, shape, 1);
+      const int s0 = default_splits(base, shape);
+      const int cands[3] = {s0, std::max(1, s0 / 2), std::min(shape.split_max, s0 * 2)};
+      for (int ci = 0; ci < 3; ++ci) {
+        if (ci > 0 && cands[ci] == cands[0]) continue;
+        if (ci == 2 && cands[2] == cands[1]) continue;
+        Tiling t = base;
+        t.splits = cands[ci];
+        const int eff = effective_splits(ctx, n, t);
+        // warm-up, then timed repetitions of MTTKRP + reduction
+        auto run = [&]() -> jkc_status {
+          JKC_TRY(enqueue_mttkrp(ctx, n, t));
+          if (eff > 1)
+            JKC_HIP(launch_reduce(ctx->partial, eff, (int32_t)ctx->dims[n], ctx->ldc, ctx->ldc,
+                                  ctx->d_colp, n == ctx->nhat ? 1 : 0, ctx->Mbuf, ctx->ldc,
+                                  ctx->stream));
+          return JKC_OK;
+        };
+        result = run();
+        if (result != JKC_OK) break;
+        if (hipEventRecord(e0, ctx->stream) != hipSuccess) { result = fail(JKC_EDEVICE, "event"); break; }
+        for (int r = 0; r < reps && result == JKC_OK; ++r) result = run();
+        if (result != JKC_OK) break;
+        if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          result = fail(JKC_EDEVICE, "event sync");
+          break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = t;
+        }
+      }
+    }
+    ctx->tiling[n] = best;
+    ctx->describe[n] = describe_tiling(best, ctx->precision);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (result == JKC_OK) g_last_error.clear();
+  return result;
+}
+
+const char* jk_cals_describe(jkc_ctx* ctx, int32_t mode) {
+  if (!ctx || mode < 0 || mode >= ctx->N) return "";
+  return ctx->describe[mode].c_str();
+}
+
+int32_t jk_cals_num_tilings(jkc_ctx* ctx) {
+  if (!ctx) return 0;
+  return (int32_t)variants_for(ctx).size();
+}
+
+jkc_status jk_cals_set_tiling(jkc_ctx* ctx, int32_t mode, int32_t variant, int32_t splits) {
+  JKC_TRY(check_ctx(ctx));
+  JKC_TRY(check_mode(ctx, mode));
+  const auto& vars = variants_for(ctx);
+  if (variant < 0 || variant >= (int)vars.size()) return fail(JKC_EINVAL, "variant out of range");
+  if (splits < 1) return fail(JKC_EINVAL, "splits must be >= 1");
+  const ModeShape shape = mode_shape(ctx, mode, ctx->split_max[mode]);
+  ctx->tiling[mode] = make_tiling(vars, variant, shape, splits);
+  ctx->describe[mode] = describe_tiling(ctx->tiling[mode], ctx->precision);
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_remove_slice(const jkc_problem* prob, const void* tensor, int32_t p, void* out) {
+  if (!prob) return fail(JKC_EINVAL, "problem is NULL");
+  if (prob->order < 2 || prob->order > kMaxOrder || !prob->dims)
+    return fail(JKC_EINVAL, "bad order/dims");
+  if (prob->sampled_mode < 0 || prob->sampled_mode >= prob->order)
+    return fail(JKC_EINVAL, "sampled_mode out of range");
+  if (!tensor || !out) return fail(JKC_EINVAL, "tensor/out is NULL");
+  if (prob->tensor_dtype != JKC_TENSOR_F64 && prob->tensor_dtype != JKC_TENSOR_F32)
+    return fail(JKC_EINVAL, "bad tensor_dtype");
+  int64_t inner = 1, outer = 1;
+  for (int n = 0; n < prob->order; ++n) {
+    if (prob->dims[n] < 1) return fail(JKC_EINVAL, "dims must be >= 1");
+    if (n < prob->sampled_mode) inner *= prob->dims[n];
+    if (n > prob->sampled_mode) outer *= prob->dims[n];
+  }
+  const int64_t I = prob->dims[prob->sampled_mode];
+  if (I < 2) return fail(JKC_EINVAL, "cannot remove the only slice");
+  if (p < 0 || p >= I) return fail(JKC_EINVAL, "p out of range");
+  JKC_HIP(launch_remove_slice(tensor, prob->tensor_dtype == JKC_TENSOR_F32 ? 4 : 8, inner,
+                              (int32_t)I, outer, p, out, static_cast<hipStream_t>(prob->stream)));
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,217 @@
+// Internal declarations of the JK-CALS library: the context, the launch
+// parameter blocks of every kernel and the launchers.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/jk_cals.h"
+
+namespace jkc {
+
+constexpr int kMaxOrder = JKC_MAX_ORDER;
+constexpr int kMaxRank = JKC_MAX_RANK;
+constexpr int kColAlign = 16;          // MFMA tile width: factor ld is a multiple
+
+// Relative pivot / eigenvalue cutoff of the normal-equation solve, times R:
+// H counts as positive definite when every Cholesky pivot exceeds
+// tau * max_j H_jj, tau = 64 * R * eps (the same reading on every path).
+constexpr double kPivotTolPerRank = 64.0 * 2.220446049250313e-16;
+
+// ---------------------------------------------------------------------------
+// MTTKRP tiling.  A block has WM x WN wavefronts; each wavefront owns a
+// (TM*16) x (TN*16) tile of the output made of 16x16 MFMA tiles; the block
+// walks the K dimension (columns of the unfolding) in steps of BK.  The K
+// range is cut into S contiguous chunks, one per grid row, whose partial
+// products are summed afterwards in a fixed order.
+// ---------------------------------------------------------------------------
+struct Tiling {
+  int variant = -1;   // index into the kernel table (precision specific)
+  int wm = 0, wn = 0, tm = 0, tn = 0, bk = 0;
+  int splits = 1;
+  int bm() const { return wm * tm * 16; }
+  int bn() const { return wn * tn * 16; }
+};
+
+struct MttkrpArgs {
+  const void* T;            // tensor (f64/f32) or bf16 hi plane (split path)
+  const void* T_lo;         // bf16 lo plane (split path only)
+  int32_t t_is_f32;         // FP64 path: tensor stored as float32
+  const double* oU[kMaxOrder - 1];   // factors of the other modes, ascending
+  int32_t odim[kMaxOrder - 1];       // their sizes
+  int64_t ostride[kMaxOrder - 1];    // their tensor strides (elements)
+  int32_t nother;           // N - 1
+  int64_t stride_n;         // tensor stride of the output mode
+  int32_t M;                // I_n (output rows)
+  int64_t J;                // columns of the unfolding
+  int64_t kchunk;           // K elements per split (multiple of BK)
+  int32_t ldc;              // leading dimension of factors and partials
+  int32_t ncols;            // columns to produce (<= ldc)
+  int32_t mtiles, ntiles;
+  int32_t splits;
+  double* partial;          // [splits][M][ldc]
+};
+
+// Kernel table entries (defined in the .hip files).
+struct MttkrpVariant {
+  int wm, wn, tm, tn, bk;
+  hipError_t (*launch)(const MttkrpArgs&, hipStream_t);
+};
+const std::vector<MttkrpVariant>& mttkrp_f64_variants();
+const std::vector<MttkrpVariant>& mttkrp_split_variants();
+
+// ---------------------------------------------------------------------------
+// Per-model batched kernels.
+// ---------------------------------------------------------------------------
+struct ModelTable {
+  const int32_t* off;     // [K] first column
+  const int32_t* rank;    // [K]
+  const int32_t* left;    // [K] left-out index or -1
+  const int64_t* goff;    // [K] offset of the model's R x R blocks in a Gram plane
+  const int32_t* order;   // [K] models sorted by decreasing cost
+  int32_t K;
+};
+
+struct UpdateArgs {
+  ModelTable mt;
+  int32_t N, n, nhat;
+  int32_t In;                     // rows of the updated mode
+  int32_t ldc;
+  const double* partial;          // [splits][In][ldc] MTTKRP partials
+  int32_t splits;
+  double* Mout;                   // [In][ldc] reduced MTTKRP (row-p zeroed)
+  double* U;                      // [In][ldc] factor of mode n (output)
+  double* G[kMaxOrder];           // Gram planes, one per mode
+  double* lambda;                 // [ldc]
+  const double* normT2;           // [K] ||T_{-p}||^2
+  double* err;                    // [K]
+  double* fit;                    // [K]
+  double* fit_prev;               // [K]
+  int32_t* status;                // [K]
+  int32_t* iters;                 // [K]
+  int32_t last_mode;              // 1 when n == N-1: evaluate the error
+  double tol;                     // convergence tolerance (<= 0: off)
+  int32_t check_conv;             // 1: update convergence flags
+};
+
+hipError_t launch_update(const UpdateArgs& a, hipStream_t s);
+
+struct GramArgs {
+  ModelTable mt;
+  int32_t rows;
+  int32_t ldc;
+  const double* U;   // [rows][ldc]
+  double* G;         // Gram plane
+};
+hipError_t launch_gram(const GramArgs& a, hipStream_t s);
+
+hipError_t launch_reduce(const double* partial, int32_t splits, int32_t rows,
+                         int32_t ldc, int32_t ncols, const int32_t* colp,
+                         int32_t zero_rows, double* out, int32_t ldo,
+                         hipStream_t s);
+
+// Preparation kernels.
+hipError_t launch_copy_tensor(const void* src, int32_t src_f32, void* dst,
+                              int64_t count, hipStream_t s);
+hipError_t launch_split_tensor(const void* src, int32_t src_f32, uint16_t* hi,
+                               uint16_t* lo, int64_t count, hipStream_t s);
+hipError_t launch_slice_norms(const void* T, int32_t t_f32, int64_t inner,
+                              int32_t I, int64_t outer, double* partial,
+                              int32_t chunks, double* s_out, hipStream_t s);
+hipError_t launch_model_norms(const double* s, int32_t I, const int32_t* left,
+                              int32_t K, double* normT2, hipStream_t st);
+hipError_t launch_pack_factor(const double* src, int32_t lds, int32_t rows,
+                              int32_t C, int32_t ldc, const int32_t* colp,
+                              int32_t zero_rows, double* dst, hipStream_t s);
+hipError_t launch_unpack(const double* src, int32_t ldc, int32_t rows,
+                         int32_t C, double* dst, hipStream_t s);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_remove_slice(const void* src, int32_t elem_bytes,
+                               int64_t inner, int32_t I, int64_t outer,
+                               int32_t p, void* dst, hipStream_t s);
+hipError_t launch_count_active(const int32_t* status, int32_t K, int32_t* out,
+                               hipStream_t s);
+
+struct GradArgs {
+  ModelTable mt;
+  int32_t N, n, nhat;
+  int32_t In, ldc;
+  const double* Mfull;     // [In][ldc] reduced MTTKRP of mode n (row-p zeroed)
+  const double* U;         // [In][ldc] factor of mode n
+  const double* Gp[kMaxOrder];   // Gram planes
+  double* grad;            // [In][ldc] gradient of mode n (out)
+  const double* normT2;    // [K]
+  double* loss;            // [K] (written when last_mode)
+  int32_t last_mode;
+};
+hipError_t launch_grad_assemble(const GradArgs& a, hipStream_t s);
+hipError_t launch_scale_cols_by_model(const ModelTable& mt, const double* w,
+                                      const double* src, int32_t rows,
+                                      int32_t ldc, double* dst, int32_t ldd,
+                                      int32_t C, hipStream_t s);
+hipError_t launch_fold_lambda(double* U, int32_t rows, int32_t ldc, int32_t C,
+                              double* lambda, hipStream_t s);
+hipError_t launch_gd_eta(const ModelTable& mt, int32_t N, const double* const* G,
+                         double* eta, hipStream_t s);
+hipError_t launch_gd_step(const ModelTable& mt, const double* eta,
+                          const int32_t* colmodel, double* U,
+                          const double* grad, int32_t rows, int32_t ldc,
+                          int32_t C, hipStream_t s);
+
+}  // namespace jkc
+
+// The context (opaque to callers).
+struct jkc_ctx {
+  // problem
+  int32_t N = 0, nhat = 0, K = 0, C = 0, ldc = 0;
+  int64_t dims[jkc::kMaxOrder] = {0, 0, 0, 0};
+  int64_t strides[jkc::kMaxOrder] = {0, 0, 0, 0};
+  int64_t P = 0;
+  int32_t tensor_f32 = 0, precision = 0;
+  hipStream_t stream = nullptr;
+  std::vector<int32_t> h_rank, h_left, h_off, h_order, h_colp, h_colmodel;
+  std::vector<int64_t> h_goff;
+  int64_t gsize = 0;  // doubles per Gram plane
+
+  // device buffers (all inside the caller's workspace)
+  const void* T = nullptr;       // FP64 path tensor (f64 or f32)
+  uint16_t* T_hi = nullptr;      // split path planes
+  uint16_t* T_lo = nullptr;
+  double* U[jkc::kMaxOrder] = {nullptr, nullptr, nullptr, nullptr};
+  double* G[jkc::kMaxOrder] = {nullptr, nullptr, nullptr, nullptr};
+  double* Mbuf = nullptr;        // [max I_n][ldc]
+  double* partial = nullptr;     // split-K partials
+  int64_t partial_doubles = 0;
+  double* lambda = nullptr;
+  double* normT2 = nullptr;
+  double* err = nullptr;
+  double* fit = nullptr;
+  double* fit_prev = nullptr;
+  int32_t* status = nullptr;
+  int32_t* iters = nullptr;
+  int32_t* d_off = nullptr;
+  int32_t* d_rank = nullptr;
+  int32_t* d_left = nullptr;
+  int32_t* d_order = nullptr;
+  int32_t* d_colp = nullptr;
+  int32_t* d_colmodel = nullptr;
+  int64_t* d_goff = nullptr;
+  double* slice = nullptr;       // [I_nhat] slice norms
+  double* slice_part = nullptr;  // [chunks][I_nhat]
+  int32_t* counter = nullptr;    // [1] active-model count
+  double* grad[jkc::kMaxOrder] = {nullptr, nullptr, nullptr, nullptr};
+  double* eta = nullptr;         // [K]
+
+  jkc::Tiling tiling[jkc::kMaxOrder];
+  int split_max[jkc::kMaxOrder] = {1, 1, 1, 1};
+  std::string describe[jkc::kMaxOrder];
+  bool lambda_is_one = true;     // lambda folded into the last factor
+
+  jkc::ModelTable table() const {
+    return jkc::ModelTable{d_off, d_rank, d_left, d_goff, d_order, K};
+  }
+};

@@ -1,0 +1,272 @@
+// Preparation and bookkeeping kernels: tensor residency (copy or bfloat16
+// hi/lo split), slice norms ||T(p,:,...)||^2 and the submodel norms
+// ||T_{-p}||^2 of the error step of Alg. 3, multi-factor packing with the
+// inserted zero row of Alg. 3's initialisation, the fixed-order reduction of
+// split-K MTTKRP partials with the Case I row removal, and the explicit
+// slice removal of Alg. 2 (used by the plain per-submodel baseline).
+#include "jkc_internal.hpp"
+
+namespace jkc {
+
+namespace {
+
+int grid_for(int64_t n, int per = 256) {
+  int64_t b = (n + per - 1) / per;
+  if (b < 1) b = 1;
+  if (b > 8192) b = 8192;
+  return (int)b;
+}
+
+__global__ void k_copy_tensor(const void* src, int32_t src_f32, void* dst, int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (src_f32)
+      static_cast<float*>(dst)[e] = static_cast<const float*>(src)[e];
+    else
+      static_cast<double*>(dst)[e] = static_cast<const double*>(src)[e];
+  }
+}
+
+// Round a float64 to bfloat16 with round-to-nearest-even, directly from the
+// float64 bits (no intermediate float32 rounding).
+__device__ uint16_t bf16_rne(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t sign = (uint32_t)(b >> 63) << 15;
+  const int e = (int)((b >> 52) & 0x7ff);
+  const uint64_t m = b & ((1ull << 52) - 1);
+  if (e == 0x7ff) return (uint16_t)(sign | 0x7f80u | (m ? 0x40u : 0u));
+  const int eb = e - 1023 + 127;
+  if (eb >= 255) return (uint16_t)(sign | 0x7f80u);
+  if (eb <= 0) {
+    if (e == 0) return (uint16_t)sign;
+    const int drop = 45 + (1 - eb);
+    if (drop > 62) return (uint16_t)sign;
+    const uint64_t full = (1ull << 52) | m;
+    uint64_t q = full >> drop;
+    const uint64_t rem = full & ((1ull << drop) - 1);
+    const uint64_t half = 1ull << (drop - 1);
+    if (rem > half || (rem == half && (q & 1))) ++q;
+    return (uint16_t)(sign | (uint32_t)q);
+  }
+  uint32_t r = ((uint32_t)eb << 7) | (uint32_t)(m >> 45);
+  const uint64_t rem = m & ((1ull << 45) - 1);
+  const uint64_t half = 1ull << 44;
+  if (rem > half || (rem == half && (r & 1))) ++r;
+  return (uint16_t)(sign | r);
+}
+
+__device__ inline double bf16_to_double(uint16_t h) {
+  return (double)__uint_as_float((uint32_t)h << 16);
+}
+
+__global__ void k_split_tensor(const void* src, int32_t src_f32, uint16_t* hi, uint16_t* lo,
+                               int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double x = src_f32 ? (double)static_cast<const float*>(src)[e]
+                             : static_cast<const double*>(src)[e];
+    const uint16_t h = bf16_rne(x);
+    hi[e] = h;
+    lo[e] = bf16_rne(x - bf16_to_double(h));
+  }
+}
+
+// Tensor viewed as (inner, I, outer): element (a, p, b) at a + inner*(p + I*b).
+// Block `chunk` sums outer indices b = chunk, chunk + chunks, ...; thread
+// handles slices p; each partial is one sequential sum.
+__global__ void k_slice_partial(const void* T, int32_t t_f32, int64_t inner, int32_t I,
+                                int64_t outer, int32_t chunks, double* part) {
+  const int chunk = blockIdx.x;
+  for (int p = threadIdx.x; p < I; p += blockDim.x) {
+    double s = 0.0;
+    for (int64_t b = chunk; b < outer; b += chunks) {
+      const int64_t base = inner * ((int64_t)p + (int64_t)I * b);
+      for (int64_t a = 0; a < inner; ++a) {
+        const double v = t_f32 ? (double)static_cast<const float*>(T)[base + a]
+                               : static_cast<const double*>(T)[base + a];
+        s += v * v;
+      }
+    }
+    part[(int64_t)chunk * I + p] = s;
+  }
+}
+
+__global__ void k_slice_final(const double* part, int32_t chunks, int32_t I, double* s_out) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < I; p += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * I + p];
+    s_out[p] = s;
+  }
+}
+
+// ||T_{-p}||^2 = sum_{i != p} s_i, ascending i (the full norm for p = -1).
+__global__ void k_model_norms(const double* s, int32_t I, const int32_t* left, int32_t K,
+                              double* normT2) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
+    const int p = left[k];
+    double t = 0.0;
+    for (int i = 0; i < I; ++i)
+      if (i != p) t += s[i];
+    normT2[k] = t;
+  }
+}
+
+// dst[i][c] (ld ldc) = src[i][c] (ld lds) for c < C, 0 for C <= c < ldc;
+// row colp[c] is zeroed when zero_rows (the inserted zero row, Alg. 3).
+__global__ void k_pack(const double* src, int32_t lds, int32_t rows, int32_t C, int32_t ldc,
+                       const int32_t* colp, int32_t zero_rows, double* dst) {
+  const int64_t n = (int64_t)rows * ldc;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / ldc;
+    const int c = (int)(e % ldc);
+    double v = 0.0;
+    if (c < C) {
+      v = src[i * lds + c];
+      if (zero_rows && colp[c] == (int)i) v = 0.0;
+    }
+    dst[e] = v;
+  }
+}
+
+__global__ void k_unpack(const double* src, int32_t ldc, int32_t rows, int32_t C, double* dst) {
+  const int64_t n = (int64_t)rows * C;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / C;
+    const int c = (int)(e % C);
+    dst[e] = src[i * ldc + c];
+  }
+}
+
+__global__ void k_fill(double* p, int64_t n, double v) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+// out[i][c] = sum_s partial[s][i][c] in ascending s; row colp[c] set to 0
+// when zero_rows (Case I: the left-out row of the sampled mode's MTTKRP).
+__global__ void k_reduce(const double* partial, int32_t splits, int32_t rows, int32_t ldc,
+                         int32_t ncols, const int32_t* colp, int32_t zero_rows, double* out,
+                         int32_t ldo) {
+  const int64_t n = (int64_t)rows * ncols;
+  const int64_t plane = (int64_t)rows * ldc;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / ncols;
+    const int c = (int)(e % ncols);
+    const int64_t at = i * ldc + c;
+    double s = 0.0;
+    for (int sp = 0; sp < splits; ++sp) s += partial[sp * plane + at];
+    if (zero_rows && colp[c] == (int)i) s = 0.0;
+    out[i * ldo + c] = s;
+  }
+}
+
+template <typename E>
+__global__ void k_remove_slice(const E* src, int64_t inner, int32_t I, int64_t outer, int32_t p,
+                               E* dst) {
+  const int64_t n = inner * (int64_t)(I - 1) * outer;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = e % inner;
+    const int64_t rest = e / inner;
+    const int64_t q = rest % (I - 1);
+    const int64_t b = rest / (I - 1);
+    const int64_t qs = q < p ? q : q + 1;
+    dst[e] = src[a + inner * (qs + (int64_t)I * b)];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_copy_tensor(const void* src, int32_t src_f32, void* dst, int64_t count,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_tensor, dim3(grid_for(count)), dim3(256), 0, s, src, src_f32, dst,
+                     count);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_tensor(const void* src, int32_t src_f32, uint16_t* hi, uint16_t* lo,
+                               int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_split_tensor, dim3(grid_for(count)), dim3(256), 0, s, src, src_f32, hi,
+                     lo, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_slice_norms(const void* T, int32_t t_f32, int64_t inner, int32_t I,
+                              int64_t outer, double* partial, int32_t chunks, double* s_out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_slice_partial, dim3(chunks), dim3(256), 0, s, T, t_f32, inner, I, outer,
+                     chunks, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_slice_final, dim3(grid_for(I)), dim3(256), 0, s, partial, chunks, I,
+                     s_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_model_norms(const double* s, int32_t I, const int32_t* left, int32_t K,
+                              double* normT2, hipStream_t st) {
+  hipLaunchKernelGGL(k_model_norms, dim3(grid_for(K)), dim3(256), 0, st, s, I, left, K, normT2);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_factor(const double* src, int32_t lds, int32_t rows, int32_t C,
+                              int32_t ldc, const int32_t* colp, int32_t zero_rows, double* dst,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_pack, dim3(grid_for((int64_t)rows * ldc)), dim3(256), 0, s, src, lds,
+                     rows, C, ldc, colp, zero_rows, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const double* src, int32_t ldc, int32_t rows, int32_t C, double* dst,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack, dim3(grid_for((int64_t)rows * C)), dim3(256), 0, s, src, ldc,
+                     rows, C, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partial, int32_t splits, int32_t rows, int32_t ldc,
+                         int32_t ncols, const int32_t* colp, int32_t zero_rows, double* out,
+                         int32_t ldo, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(grid_for((int64_t)rows * ncols)), dim3(256), 0, s, partial,
+                     splits, rows, ldc, ncols, colp, zero_rows, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_remove_slice(const void* src, int32_t elem_bytes, int64_t inner, int32_t I,
+                               int64_t outer, int32_t p, void* dst, hipStream_t s) {
+  const int64_t n = inner * (int64_t)(I - 1) * outer;
+  if (n <= 0) return hipSuccess;
+  if (elem_bytes == 4)
+    hipLaunchKernelGGL(k_remove_slice<float>, dim3(grid_for(n)), dim3(256), 0, s,
+                       static_cast<const float*>(src), inner, I, outer, p,
+                       static_cast<float*>(dst));
+  else
+    hipLaunchKernelGGL(k_remove_slice<double>, dim3(grid_for(n)), dim3(256), 0, s,
+                       static_cast<const double*>(src), inner, I, outer, p,
+                       static_cast<double*>(dst));
+  return hipGetLastError();
+}
+
+}  // namespace jkc

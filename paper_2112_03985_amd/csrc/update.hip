@@ -1,0 +1,543 @@
+// Per-model batched kernels of JK-CALS: everything after the fused MTTKRP
+// that stays separate for each submodel (Alg. 3, the per-p loop inside the
+// mode loop, and the error step).
+//
+// One 256-thread block handles one model at a time and strides over the
+// models in decreasing-cost order (a persistent grid), so batches of
+// uneven ranks keep every block busy.  For model k of rank R (<= 32) the
+// update of mode n is:
+//   H = *_{m != n} G_m|k                        (Hadamard of Gramians)
+//   H = L L^T                                    (Cholesky; eigen
+//                                                 pseudoinverse fallback)
+//   U_n|k(i,:) = M_n|k(i,:) H^{-1}  for all rows (normal equations)
+//   row p of M is taken as 0 when n is the sampled mode (Case I; the
+//   re-zeroing step of Alg. 3 then holds automatically: 0 H^{-1} = 0)
+//   lambda_r = ||U(:,r)||, U(:,r) /= lambda_r    (normalisation)
+//   G_n|k = U^T U, upper triangle mirrored       (exactly symmetric)
+// and after the last mode the submodel error with ||T_{-p}||^2 (Alg. 3
+// error step, with the identity's Gram term read with a plus sign).
+// Every reduction runs in a fixed order, so results are bitwise repeatable.
+#include "jkc_internal.hpp"
+
+namespace jkc {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kLd = kMaxRank + 1;   // LDS row pitch of R x R matrices
+
+__device__ inline double wave_sum(double v) {
+  // Butterfly over the 64 lanes; the same lanes combine in the same order on
+  // every run.
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// H for model k: product of the other modes' Gram blocks in ascending mode
+// order (the oracle's order).
+__device__ void build_h(const double* G0, const double* G1, const double* G2, const double* G3,
+                        int N, int n, int64_t goff, int R, double (*H)[kLd]) {
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
+    const int r = e / R, s = e % R;
+    const int64_t at = goff + r * R + s;
+    double h = 0.0;
+    bool first = true;
+#pragma unroll
+    for (int m = 0; m < kMaxOrder; ++m) {
+      if (m >= N || m == n) continue;
+      const double* Gm = m == 0 ? G0 : m == 1 ? G1 : m == 2 ? G2 : G3;
+      const double g = Gm[at];
+      h = first ? g : h * g;
+      first = false;
+    }
+    H[r][s] = h;
+  }
+}
+
+// Cholesky H = L L^T (lower).  Returns false (block-uniform) when a pivot is
+// not finite or at or below tau * max_j H_jj.
+__device__ bool cholesky(const double (*H)[kLd], double (*L)[kLd], int R, int* s_flag) {
+  if (threadIdx.x == 0) *s_flag = 1;
+  __syncthreads();
+  double maxdiag = 0.0;
+  for (int j = 0; j < R; ++j) maxdiag = fmax(maxdiag, H[j][j]);
+  const double thresh = kPivotTolPerRank * R * maxdiag;
+  for (int j = 0; j < R; ++j) {
+    if (threadIdx.x == 0) {
+      double d = H[j][j];
+      for (int q = 0; q < j; ++q) d -= L[j][q] * L[j][q];
+      const bool ok = isfinite(d) && d > thresh && maxdiag > 0.0 && isfinite(maxdiag);
+      if (!ok) *s_flag = 0;
+      L[j][j] = ok ? sqrt(d) : 1.0;
+    }
+    __syncthreads();
+    const int i = threadIdx.x;
+    if (i > j && i < R) {
+      double v = H[i][j];
+      for (int q = 0; q < j; ++q) v -= L[i][q] * L[j][q];
+      L[i][j] = v / L[j][j];
+    }
+    __syncthreads();
+  }
+  const bool ok = *s_flag != 0;
+  __syncthreads();
+  return ok;
+}
+
+// Eigen pseudoinverse of symmetric H by cyclic Jacobi rotations (fallback
+// only).  Writes Hp = V diag(w^+) V^T with eigenvalues at or below
+// tau * w_max treated as zero.  W and V are LDS scratch.
+__device__ void jacobi_pinv(const double (*H)[kLd], double (*W)[kLd], double (*V)[kLd],
+                            double (*Hp)[kLd], int R, double* s_cs) {
+  const int t = threadIdx.x;
+  for (int e = t; e < R * R; e += blockDim.x) {
+    const int r = e / R, s = e % R;
+    W[r][s] = H[r][s];
+    V[r][s] = (r == s) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    // off-diagonal mass, computed by one thread in a fixed order
+    if (t == 0) {
+      double off = 0.0, tot = 0.0;
+      for (int r = 0; r < R; ++r)
+        for (int s = 0; s < R; ++s) {
+          tot += W[r][s] * W[r][s];
+          if (r != s) off += W[r][s] * W[r][s];
+        }
+      s_cs[2] = (off <= 1e-30 * tot || !isfinite(off)) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (s_cs[2] != 0.0) break;
+    for (int p = 0; p < R - 1; ++p)
+      for (int q = p + 1; q < R; ++q) {
+        if (t == 0) {
+          const double apq = W[p][q];
+          double c = 1.0, s = 0.0;
+          if (apq != 0.0) {
+            const double theta = (W[q][q] - W[p][p]) / (2.0 * apq);
+            const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(tt * tt + 1.0);
+            s = tt * c;
+          }
+          s_cs[0] = c;
+          s_cs[1] = s;
+        }
+        __syncthreads();
+        const double c = s_cs[0], s = s_cs[1];
+        if (s != 0.0) {
+          // columns p, q of W and V
+          if (t < R) {
+            const double wp = W[t][p], wq = W[t][q];
+            W[t][p] = c * wp - s * wq;
+            W[t][q] = s * wp + c * wq;
+            const double vp = V[t][p], vq = V[t][q];
+            V[t][p] = c * vp - s * vq;
+            V[t][q] = s * vp + c * vq;
+          }
+          __syncthreads();
+          // rows p, q of W
+          if (t < R) {
+            const double wp = W[p][t], wq = W[q][t];
+            W[p][t] = c * wp - s * wq;
+            W[q][t] = s * wp + c * wq;
+          }
+        }
+        __syncthreads();
+      }
+  }
+  if (t == 0) {
+    double wmax = 0.0;
+    for (int r = 0; r < R; ++r) wmax = fmax(wmax, W[r][r]);
+    s_cs[3] = kPivotTolPerRank * R * wmax;
+  }
+  __syncthreads();
+  const double cutoff = s_cs[3];
+  for (int e = t; e < R * R; e += blockDim.x) {
+    const int r = e / R, s = e % R;
+    double acc = 0.0;
+    for (int q = 0; q < R; ++q) {
+      const double w = W[q][q];
+      if (w > cutoff) acc += V[r][q] * (1.0 / w) * V[s][q];
+    }
+    Hp[r][s] = acc;
+  }
+  __syncthreads();
+}
+
+// Inverse of H from its Cholesky factor: Linv = L^{-1} by forward
+// substitution (one column per thread), then H^{-1} = Linv^T Linv with the
+// upper triangle mirrored (exactly symmetric).
+__device__ void cholesky_inverse(const double (*L)[kLd], double (*Linv)[kLd],
+                                 double (*Hinv)[kLd], int R) {
+  const int j = threadIdx.x;
+  if (j < R) {
+    for (int r = 0; r < R; ++r) {
+      double v = (r == j) ? 1.0 : 0.0;
+      for (int q = j; q < r; ++q) v -= L[r][q] * Linv[q][j];
+      Linv[r][j] = (r < j) ? 0.0 : v / L[r][r];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
+    const int r = e / R, s = e % R;
+    if (r <= s) {
+      double acc = 0.0;
+      for (int q = s; q < R; ++q) acc += Linv[q][r] * Linv[q][s];
+      Hinv[r][s] = acc;
+      Hinv[s][r] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+// Row pass: U(i,:) = M(i,:) H^{-1} for every row i of the model's block (row
+// `zero_row` of M taken as 0); returns this thread's share of
+// sum_i U(i,:) . M(i,:) (for the error identity).
+__device__ double row_pass(const double* __restrict__ M, double* __restrict__ U, int rows,
+                           int ldc, int off, int R, int zero_row, const double (*Hinv)[kLd]) {
+  double inner = 0.0;
+  for (int e = threadIdx.x; e < rows * R; e += blockDim.x) {
+    const int i = e / R, r = e % R;
+    const double* mrow = M + (int64_t)i * ldc + off;
+    double u = 0.0, m = 0.0;
+    if (i != zero_row) {
+      for (int q = 0; q < R; ++q) u += mrow[q] * Hinv[q][r];
+      m = mrow[r];
+    }
+    U[(int64_t)i * ldc + off + r] = u;
+    inner += u * m;
+  }
+  return inner;
+}
+
+// Column sums of squares of the model's block of U, one column per wave
+// round, lanes striding rows; then a fixed butterfly.
+__device__ void column_norms(const double* U, int rows, int ldc, int off, int R, double* lam) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  for (int r = wave; r < R; r += nw) {
+    double s = 0.0;
+    for (int i = lane; i < rows; i += 64) {
+      const double v = U[(int64_t)i * ldc + off + r];
+      s += v * v;
+    }
+    s = wave_sum(s);
+    if (lane == 0) lam[r] = sqrt(s);
+  }
+}
+
+// G = U^T U on the model's block, upper triangle computed, then mirrored.
+__device__ void gram_block(const double* U, int rows, int ldc, int off, int R, double* G,
+                           double (*Gs)[kLd]) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  const int npairs = R * (R + 1) / 2;
+  for (int pr = wave; pr < npairs; pr += nw) {
+    // pair index -> (r, s), r <= s, row-major over the upper triangle
+    int r = 0, rem = pr;
+    while (rem >= R - r) {
+      rem -= R - r;
+      ++r;
+    }
+    const int s = r + rem;
+    double acc = 0.0;
+    for (int i = lane; i < rows; i += 64) {
+      const double* row = U + (int64_t)i * ldc + off;
+      acc += row[r] * row[s];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      G[r * R + s] = acc;
+      G[s * R + r] = acc;
+      if (Gs) {
+        Gs[r][s] = acc;
+        Gs[s][r] = acc;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_update(const UpdateArgs a) {
+  __shared__ double H[kMaxRank][kLd];
+  __shared__ double L[kMaxRank][kLd];
+  __shared__ double Hp[kMaxRank][kLd];
+  __shared__ double Wj[kMaxRank][kLd];
+  __shared__ double Vj[kMaxRank][kLd];
+  __shared__ double Gs[kMaxRank][kLd];
+  __shared__ double s_lam[kMaxRank];
+  __shared__ double s_red[kThreads];
+  __shared__ double s_cs[4];
+  __shared__ int s_flag;
+
+  for (int idx = blockIdx.x; idx < a.mt.K; idx += gridDim.x) {
+    const int k = a.mt.order[idx];
+    const int32_t st = a.status[k];
+    if (st & (JKC_ST_CONVERGED | JKC_ST_NONFINITE)) continue;  // frozen (block-uniform)
+    const int R = a.mt.rank[k];
+    const int off = a.mt.off[k];
+    const int p = a.mt.left[k];
+    const int64_t goff = a.mt.goff[k];
+    const int zero_row = (a.n == a.nhat) ? p : -1;
+
+    build_h(a.G[0], a.G[1], a.G[2], a.G[3], a.N, a.n, goff, R, H);
+    __syncthreads();
+    const bool chol_ok = cholesky(H, L, R, &s_flag);
+    if (chol_ok)
+      cholesky_inverse(L, Wj, Hp, R);
+    else
+      jacobi_pinv(H, Wj, Vj, Hp, R, s_cs);
+
+    const double inner = row_pass(a.Mout, a.U, a.In, a.ldc, off, R, zero_row, Hp);
+    s_red[threadIdx.x] = inner;
+    __syncthreads();
+
+    column_norms(a.U, a.In, a.ldc, off, R, s_lam);
+    __syncthreads();
+    for (int e = threadIdx.x; e < a.In * R; e += blockDim.x) {
+      const int i = e / R, r = e % R;
+      const double l = s_lam[r];
+      if (l > 0.0) {
+        double* u = a.U + (int64_t)i * a.ldc + off + r;
+        *u = *u / l;
+      }
+    }
+    __syncthreads();
+    double* Gn = a.n == 0 ? a.G[0] : a.n == 1 ? a.G[1] : a.n == 2 ? a.G[2] : a.G[3];
+    gram_block(a.U, a.In, a.ldc, off, R, Gn + goff, Gs);
+    if (threadIdx.x < R) a.lambda[off + threadIdx.x] = s_lam[threadIdx.x];
+    __syncthreads();
+
+    if (threadIdx.x == 0) {
+      int32_t nst = st | (chol_ok ? 0 : JKC_ST_FALLBACK);
+      if (a.last_mode) {
+        double in = 0.0;
+        for (int t = 0; t < (int)blockDim.x; ++t) in += s_red[t];
+        double quad = 0.0;
+        for (int r = 0; r < R; ++r)
+          for (int s = 0; s < R; ++s) quad += s_lam[r] * H[r][s] * Gs[r][s] * s_lam[s];
+        const double nt2 = a.normT2[k];
+        const double e = nt2 + quad - 2.0 * in;
+        const double f = 1.0 - sqrt(fmax(e, 0.0)) / sqrt(nt2);
+        const int it = a.iters[k] + 1;
+        a.iters[k] = it;
+        a.err[k] = e;
+        if (!isfinite(e)) nst |= JKC_ST_NONFINITE;
+        if (a.check_conv && a.tol > 0.0 && it >= 2 && fabs(f - a.fit_prev[k]) < a.tol)
+          nst |= JKC_ST_CONVERGED;
+        a.fit_prev[k] = f;
+        a.fit[k] = f;
+      }
+      a.status[k] = nst;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_gram(const GramArgs a) {
+  for (int idx = blockIdx.x; idx < a.mt.K; idx += gridDim.x) {
+    const int k = a.mt.order[idx];
+    gram_block(a.U, a.rows, a.ldc, a.mt.off[k], a.mt.rank[k], a.G + a.mt.goff[k], nullptr);
+    __syncthreads();
+  }
+}
+
+int persistent_grid(int K) {
+  // enough resident blocks to cover all 256 compute units a few times over
+  return K < 1024 ? K : 1024;
+}
+
+// Gradient of the CP loss for one mode (all-at-once CP), per model:
+// grad = U H - M with H = *_{m != n} G_m; row p of the sampled mode is 0.
+// After the last mode the loss 1/2 (||T_{-p}||^2 + sum(H*G) - 2 sum(U*M)).
+__global__ void __launch_bounds__(kThreads) k_grad(const GradArgs a) {
+  __shared__ double H[kMaxRank][kLd];
+  __shared__ double s_red[kThreads];
+  for (int idx = blockIdx.x; idx < a.mt.K; idx += gridDim.x) {
+    const int k = a.mt.order[idx];
+    const int R = a.mt.rank[k];
+    const int off = a.mt.off[k];
+    const int p = a.mt.left[k];
+    const int64_t goff = a.mt.goff[k];
+    build_h(a.Gp[0], a.Gp[1], a.Gp[2], a.Gp[3], a.N, a.n, goff, R, H);
+    __syncthreads();
+    double inner = 0.0;
+    for (int e = threadIdx.x; e < a.In * R; e += blockDim.x) {
+      const int i = e / R, r = e % R;
+      const double* urow = a.U + (int64_t)i * a.ldc + off;
+      double g = 0.0;
+      const double m = a.Mfull[(int64_t)i * a.ldc + off + r];
+      if (!(a.n == a.nhat && i == p)) {
+        double uh = 0.0;
+        for (int q = 0; q < R; ++q) uh += urow[q] * H[q][r];
+        g = uh - m;
+      }
+      a.grad[(int64_t)i * a.ldc + off + r] = g;
+      inner += urow[r] * m;
+    }
+    s_red[threadIdx.x] = inner;
+    __syncthreads();
+    if (a.last_mode && threadIdx.x == 0) {
+      double in = 0.0;
+      for (int t = 0; t < (int)blockDim.x; ++t) in += s_red[t];
+      const double* Gn = (a.n == 0 ? a.Gp[0] : a.n == 1 ? a.Gp[1] : a.n == 2 ? a.Gp[2] : a.Gp[3]) + goff;
+      double quad = 0.0;
+      for (int r = 0; r < R; ++r)
+        for (int s = 0; s < R; ++s) quad += H[r][s] * Gn[r * R + s];
+      a.loss[k] = 0.5 * (a.normT2[k] + quad - 2.0 * in);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_scale_cols(const ModelTable mt, const double* w, const int32_t* colmodel_unused,
+                             const double* src, int32_t rows, int32_t ldc, double* dst,
+                             int32_t ldd, int32_t C) {
+  (void)colmodel_unused;
+  for (int idx = blockIdx.x; idx < mt.K; idx += gridDim.x) {
+    const int R = mt.rank[idx], off = mt.off[idx];
+    const double s = w ? w[idx] : 1.0;
+    for (int e = threadIdx.x; e < rows * R; e += blockDim.x) {
+      const int i = e / R, r = e % R;
+      dst[(int64_t)i * ldd + off + r] = s * src[(int64_t)i * ldc + off + r];
+    }
+  }
+  (void)C;
+}
+
+__global__ void k_fold_lambda(double* U, int32_t rows, int32_t ldc, int32_t C, double* lambda) {
+  const int64_t n = (int64_t)rows * C;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / C;
+    const int c = (int)(e % C);
+    U[i * ldc + c] *= lambda[c];
+  }
+}
+
+__global__ void k_reset_lambda(double* lambda, int32_t C) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x)
+    lambda[c] = 1.0;
+}
+
+// eta_k = 1 / sum_n ||H_n|k||_F from the current Gram planes.
+__global__ void k_gd_eta(const ModelTable mt, int32_t N, const double* G0, const double* G1,
+                         const double* G2, const double* G3, double* eta) {
+  const double* G[kMaxOrder] = {G0, G1, G2, G3};
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < mt.K; k += gridDim.x * blockDim.x) {
+    const int R = mt.rank[k];
+    const int64_t goff = mt.goff[k];
+    double tot = 0.0;
+    for (int n = 0; n < N; ++n) {
+      double f2 = 0.0;
+      for (int r = 0; r < R; ++r)
+        for (int s = 0; s < R; ++s) {
+          double h = 0.0;
+          bool first = true;
+          for (int m = 0; m < N; ++m) {
+            if (m == n) continue;
+            const double g = G[m][goff + r * R + s];
+            h = first ? g : h * g;
+            first = false;
+          }
+          f2 += h * h;
+        }
+      tot += sqrt(f2);
+    }
+    eta[k] = 1.0 / tot;
+  }
+}
+
+__global__ void k_gd_step(const double* eta, const int32_t* colmodel, double* U,
+                          const double* grad, int32_t rows, int32_t ldc, int32_t C) {
+  const int64_t n = (int64_t)rows * C;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / C;
+    const int c = (int)(e % C);
+    const int64_t at = i * ldc + c;
+    U[at] -= eta[colmodel[c]] * grad[at];
+  }
+}
+
+__global__ void k_count_active(const int32_t* status, int32_t K, int32_t* out) {
+  __shared__ int s[256];
+  int c = 0;
+  for (int k = threadIdx.x; k < K; k += blockDim.x)
+    c += (status[k] & (JKC_ST_CONVERGED | JKC_ST_NONFINITE)) ? 0 : 1;
+  s[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int i = 0; i < (int)blockDim.x; ++i) t += s[i];
+    out[0] = t;
+  }
+}
+
+int grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b < 1) b = 1;
+  if (b > 4096) b = 4096;
+  return (int)b;
+}
+
+}  // namespace
+
+hipError_t launch_update(const UpdateArgs& a, hipStream_t s) {
+  if (a.mt.K <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_update, dim3(persistent_grid(a.mt.K)), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(const GramArgs& a, hipStream_t s) {
+  if (a.mt.K <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gram, dim3(persistent_grid(a.mt.K)), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_assemble(const GradArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad, dim3(persistent_grid(a.mt.K)), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_cols_by_model(const ModelTable& mt, const double* w, const double* src,
+                                      int32_t rows, int32_t ldc, double* dst, int32_t ldd,
+                                      int32_t C, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_cols, dim3(persistent_grid(mt.K)), dim3(kThreads), 0, s, mt, w,
+                     nullptr, src, rows, ldc, dst, ldd, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_lambda(double* U, int32_t rows, int32_t ldc, int32_t C, double* lambda,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_fold_lambda, dim3(grid_for((int64_t)rows * C)), dim3(256), 0, s, U, rows,
+                     ldc, C, lambda);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reset_lambda, dim3(grid_for(C)), dim3(256), 0, s, lambda, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_gd_eta(const ModelTable& mt, int32_t N, const double* const* G, double* eta,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_gd_eta, dim3(grid_for(mt.K)), dim3(256), 0, s, mt, N, G[0], G[1],
+                     N > 2 ? G[2] : nullptr, N > 3 ? G[3] : nullptr, eta);
+  return hipGetLastError();
+}
+
+hipError_t launch_gd_step(const ModelTable& mt, const double* eta, const int32_t* colmodel,
+                          double* U, const double* grad, int32_t rows, int32_t ldc, int32_t C,
+                          hipStream_t s) {
+  (void)mt;
+  hipLaunchKernelGGL(k_gd_step, dim3(grid_for((int64_t)rows * C)), dim3(256), 0, s, eta,
+                     colmodel, U, grad, rows, ldc, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_active(const int32_t* status, int32_t K, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, s, status, K, out);
+  return hipGetLastError();
+}
+
+}  // namespace jkc

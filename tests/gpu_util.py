@@ -1,0 +1,59 @@
+"""Shared helpers of the GPU parity tests (not collected by pytest)."""
+import sys
+
+import numpy as np
+
+import oracle
+
+
+def say(*a):
+    """Name the case before each GPU step, flushed, so a crash still shows it."""
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def device_inputs(wl):
+    import torch
+    import paper_2112_03985_amd as jk
+    T = jk.to_device_tensor(wl.T)
+    init = [torch.from_numpy(np.ascontiguousarray(u)).cuda() for u in wl.init]
+    return T, init
+
+
+def make_ctx(wl, precision=0, copy_tensor=True):
+    import paper_2112_03985_amd as jk
+    T, init = device_inputs(wl)
+    return jk.JkCals(T, wl.dims, wl.sampled_mode, wl.ranks, wl.left_out, init,
+                     precision=precision, copy_tensor=copy_tensor)
+
+
+def cols(wl, k):
+    off = oracle.model_offsets(wl.ranks)
+    return slice(int(off[k]), int(off[k] + wl.ranks[k]))
+
+
+def oracle_model_mttkrp(wl, k, n, factors=None):
+    """Per-submodel MTTKRP by definition: reduced tensor, reduced factors,
+    output padded with a zero row at p for the sampled mode."""
+    src = wl.init if factors is None else factors
+    c = cols(wl, k)
+    U = [np.array(src[m][:, c], dtype=np.float64) for m in range(len(wl.dims))]
+    p = int(wl.left_out[k])
+    nh = wl.sampled_mode
+    U[nh] = oracle.reduce_init(U[nh], p)
+    Tk = oracle.reduce_tensor(np.asarray(wl.T, dtype=np.float64), nh, p)
+    M = oracle.mttkrp(Tk, U, n)
+    if n == nh and p >= 0:
+        M = np.insert(M, p, 0.0, axis=0)
+    return M
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()

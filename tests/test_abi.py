@@ -1,0 +1,126 @@
+"""The C ABI without a GPU: the library loads, exports every function the
+header declares, the header is valid C, and argument validation rejects bad
+input before any device work (all calls here stop at validation)."""
+import ctypes
+import os
+import shutil
+import subprocess
+
+import pytest
+
+import paper_2112_03985_amd as jk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(jk.LIB_PATH):
+        pytest.fail("libjkcals.so is not built; run python -m paper_2112_03985_amd.build")
+    return jk.lib()
+
+
+def test_exports_every_header_function(L):
+    names = jk.header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_header_is_valid_c(tmp_path):
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    src = tmp_path / "t.c"
+    src.write_text('#include "jk_cals.h"\nint main(void){jkc_problem p; (void)p; return JKC_OK;}\n')
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                        "-c", str(src), "-o", str(tmp_path / "t.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
+def _size(**kw):
+    args = dict(dims=[4, 5, 6], sampled_mode=0, ranks=[2, 3], left_out=[-1, 3])
+    args.update(kw)
+    return jk.jk_cals_workspace_size(**args)
+
+
+def test_workspace_size_valid_problem():
+    s = _size()
+    assert s > 4 * 5 * 6 * 8
+    assert s % 256 == 0
+    assert _size(ranks=[32] * 20, left_out=[-1] * 20) > s
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(dims=[4]), "order"),
+    (dict(dims=[2, 2, 2, 2, 2]), "order"),
+    (dict(dims=[4, 0, 6]), "dims"),
+    (dict(sampled_mode=3), "sampled_mode"),
+    (dict(sampled_mode=-1), "sampled_mode"),
+    (dict(ranks=[0, 3]), "rank"),
+    (dict(ranks=[33, 3]), "rank"),
+    (dict(left_out=[-2, 3]), "left_out"),
+    (dict(left_out=[-1, 4]), "left_out"),
+    (dict(dims=[1, 5, 6], left_out=[-1, 0]), "only sample"),
+    (dict(precision=2), "precision"),
+    (dict(tensor_dtype=5), "tensor_dtype"),
+    (dict(precision=1, copy_tensor=0), "copy_tensor"),
+    (dict(copy_tensor=3), "copy_tensor"),
+])
+def test_invalid_problems_rejected(kw, msg):
+    with pytest.raises(jk.JkcError) as e:
+        _size(**kw)
+    assert e.value.status == jk.JKC_EINVAL
+    assert msg in str(e.value)
+
+
+def test_null_arguments_rejected(L):
+    assert L.jk_cals_workspace_size(None, None) == jk.JKC_EINVAL
+    prob, keep = jk.make_problem([4, 5, 6], 0, [2], [-1])
+    size = ctypes.c_size_t(0)
+    assert L.jk_cals_workspace_size(ctypes.byref(prob), None) == jk.JKC_EINVAL
+    assert L.jk_cals_workspace_size(ctypes.byref(prob), ctypes.byref(size)) == jk.JKC_OK
+    assert jk.jk_cals_last_error() == ""
+    ctx = ctypes.c_void_p(0)
+    ptrs = (ctypes.c_void_p * 3)(0x1000, 0x1000, 0x1000)
+    # NULL tensor, NULL init, NULL/misaligned/too-small workspace: all
+    # rejected before anything touches the device
+    assert L.jk_cals_init(ctypes.byref(prob), None, ptrs, ctypes.c_void_p(0x100000), size, ctypes.byref(ctx)) == jk.JKC_EINVAL
+    assert "tensor" in jk.jk_cals_last_error()
+    assert L.jk_cals_init(ctypes.byref(prob), ctypes.c_void_p(0x1000), None, ctypes.c_void_p(0x100000), size, ctypes.byref(ctx)) == jk.JKC_EINVAL
+    bad = (ctypes.c_void_p * 3)(0x1000, None, 0x1000)
+    assert L.jk_cals_init(ctypes.byref(prob), ctypes.c_void_p(0x1000), bad, ctypes.c_void_p(0x100000), size, ctypes.byref(ctx)) == jk.JKC_EINVAL
+    assert L.jk_cals_init(ctypes.byref(prob), ctypes.c_void_p(0x1000), ptrs, None, size, ctypes.byref(ctx)) == jk.JKC_EINVAL
+    assert L.jk_cals_init(ctypes.byref(prob), ctypes.c_void_p(0x1000), ptrs, ctypes.c_void_p(0x100001), size, ctypes.byref(ctx)) == jk.JKC_EINVAL
+    assert "aligned" in jk.jk_cals_last_error()
+    assert L.jk_cals_init(ctypes.byref(prob), ctypes.c_void_p(0x1000), ptrs, ctypes.c_void_p(0x100000), ctypes.c_size_t(size.value - 1), ctypes.byref(ctx)) == jk.JKC_ENOMEM
+    assert L.jk_cals_init(ctypes.byref(prob), ctypes.c_void_p(0x1000), ptrs, ctypes.c_void_p(0x100000), size, None) == jk.JKC_EINVAL
+    assert ctx.value is None
+
+
+def test_null_context_rejected(L):
+    assert L.jk_cals_mttkrp(None, 0, ctypes.c_void_p(0x1000)) == jk.JKC_EINVAL
+    assert L.jk_cals_sweep(None, 1, None) == jk.JKC_EINVAL
+    assert L.jk_cals_fit(None, 1, 0.0, None, None, None) == jk.JKC_EINVAL
+    assert L.jk_cals_get_factors(None, 0, ctypes.c_void_p(0x1000), None) == jk.JKC_EINVAL
+    assert L.jk_cals_set_factors(None, 0, ctypes.c_void_p(0x1000), None) == jk.JKC_EINVAL
+    assert L.jk_cals_get_status(None, None, None, None, None) == jk.JKC_EINVAL
+    assert L.jk_cals_loss_grad(None, None) == jk.JKC_EINVAL
+    assert L.jk_cals_get_grad(None, 0, None, ctypes.c_void_p(0x1000)) == jk.JKC_EINVAL
+    assert L.jk_cals_refine(None, 1, None) == jk.JKC_EINVAL
+    assert L.jk_cals_tune(None, 1) == jk.JKC_EINVAL
+    assert L.jk_cals_set_tiling(None, 0, 0, 1) == jk.JKC_EINVAL
+    assert L.jk_cals_num_tilings(None) == 0
+    assert L.jk_cals_describe(None, 0) == b""
+    L.jk_cals_destroy(None)
+
+
+def test_remove_slice_validation(L):
+    prob, keep = jk.make_problem([4, 5, 6], 1, [1], [-1])
+    t, o = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    assert L.jk_cals_remove_slice(ctypes.byref(prob), t, 5, o) == jk.JKC_EINVAL
+    assert L.jk_cals_remove_slice(ctypes.byref(prob), t, -1, o) == jk.JKC_EINVAL
+    assert L.jk_cals_remove_slice(ctypes.byref(prob), None, 0, o) == jk.JKC_EINVAL
+    assert L.jk_cals_remove_slice(None, t, 0, o) == jk.JKC_EINVAL
+    prob1, keep1 = jk.make_problem([4, 1, 6], 1, [1], [-1])
+    assert L.jk_cals_remove_slice(ctypes.byref(prob1), t, 0, o) == jk.JKC_EINVAL
