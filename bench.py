@@ -1,0 +1,185 @@
+"""Benchmark of the JK-CALS hot path on one MI355X.
+
+One step = one complete leave-one-out jackknife of the benchmark workload on
+the GPU: tensor residency and slice norms, multi-factor packing (context
+init from device-resident inputs), then the fixed budget of concurrent ALS
+sweeps (fused MTTKRP, slice correction, batched Gram / Cholesky / update /
+normalisation, per-submodel error).  Workload: 100 x 200 x 200 float64
+tensor shaped like fluorescence data (rank 5, 2 % noise), 100 leave-one-out
+submodels of rank 5, 100 sweeps each (the fixed-iteration protocol).
+
+Prints one JSON line.  `value` = submodels fitted per second.  Also reported:
+the MTTKRP kernel's roofline position (float64 MFMA), the same jackknife done
+the plain way on the same GPU (one submodel at a time on its explicitly
+reduced tensor), and the CPU oracle's rate on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense float64 matrix peak (datasheet)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--sweeps", type=int, default=100)
+    ap.add_argument("--tune", action="store_true", help="autotune MTTKRP tilings before timing")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain per-submodel GPU baseline")
+    ap.add_argument("--plain-models", type=int, default=10)
+    ap.add_argument("--cpu-models", type=int, default=3)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2112_03985_amd as jk
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    wl = synth.config2()
+    K, C, P = wl.K, wl.C, int(np.prod(wl.dims))
+    sweeps = args.sweeps
+    T = jk.to_device_tensor(wl.T)
+    init = [torch.from_numpy(np.ascontiguousarray(u)).cuda() for u in wl.init]
+    torch.cuda.synchronize()
+
+    tiling = None
+    if args.tune:
+        ctx = jk.JkCals(T, wl.dims, 0, wl.ranks, wl.left_out, init)
+        ctx.tune(5)
+        tiling = [ctx.describe(n) for n in range(3)]
+        del ctx
+
+    def step(profile=False):
+        ctx = jk.JkCals(T, wl.dims, 0, wl.ranks, wl.left_out, init)
+        if profile:
+            ctx.profile(True)
+        ctx.sweep(sweeps)
+        return ctx
+
+    print("[bench] warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        c = step()
+    torch.cuda.synchronize()
+    desc = [c.describe(n) for n in range(3)]
+    del c
+
+    print("[bench] timing %d steps" % args.steps, file=sys.stderr, flush=True)
+    launches = np.zeros(3, np.int64)
+    kms = np.zeros(3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        c = step(profile=True)
+        n_, ms_ = c.profile_read()          # synchronises this step's stream
+        launches += n_
+        kms += ms_
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec = t1 - t0
+    ms_per_step = 1000.0 * sec / args.steps
+    value = K * args.steps / sec
+
+    # fit quality of the last step (sanity, not timed)
+    fit = c.get_status()[1].cpu().numpy()
+    del c
+
+    flops_per_launch = 2.0 * C * P          # fused MTTKRP of one mode (Sec. 4.2)
+    avg_ms = float(kms.sum() / max(launches.sum(), 1))
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "kernel": "k_mttkrp_f64", "avg_launch_ms": round(avg_ms, 5),
+                "per_mode_avg_ms": [round(float(kms[n] / max(launches[n], 1)), 5) for n in range(3)],
+                "flops_per_launch": flops_per_launch}
+
+    out = {"metric": "jackknife submodels fitted/sec (JK-CALS, 100 sweeps each)",
+           "value": round(value, 2), "unit": "submodels/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "c2: 100x200x200 f64 fluorescence-like tensor, rank 5, 2% noise; "
+                                  "100 leave-one-out submodels of rank 5; 100 ALS sweeps",
+                      "dims": list(wl.dims), "models": K, "rank": 5, "columns": C, "sweeps": sweeps,
+                      "tiling": tiling or desc},
+           "mttkrp_tflops": round(achieved, 3),
+           "roofline": roofline,
+           "fit_range": [round(float(fit.min()), 6), round(float(fit.max()), 6)]}
+
+    if not args.no_plain:
+        print("[bench] plain per-submodel ALS on the GPU (%d models)" % args.plain_models,
+              file=sys.stderr, flush=True)
+        n_plain = min(args.plain_models, K)
+        dims_red = [wl.dims[0] - 1] + list(wl.dims[1:])
+        buf = torch.empty(P // wl.dims[0] * dims_red[0], dtype=torch.float64, device="cuda")
+        cols = np.arange(C).reshape(K, 5)
+        # per-submodel inputs prepared before timing: the reduced init rows
+        inits = []
+        for k in range(n_plain):
+            p = int(wl.left_out[k])
+            keep = [i for i in range(wl.dims[0]) if i != p]
+            inits.append([torch.from_numpy(np.ascontiguousarray(wl.init[0][keep][:, cols[k]])).cuda(),
+                          torch.from_numpy(np.ascontiguousarray(wl.init[1][:, cols[k]])).cuda(),
+                          torch.from_numpy(np.ascontiguousarray(wl.init[2][:, cols[k]])).cuda()])
+
+        def plain_one(k):
+            jk.jk_cals_remove_slice(T, wl.dims, 0, int(wl.left_out[k]), out=buf)
+            cx = jk.JkCals(buf, dims_red, 0, [5], [-1], inits[k], copy_tensor=False)
+            cx.sweep(sweeps)
+            return cx
+
+        cx = plain_one(0)
+        torch.cuda.synchronize()
+        del cx
+        t0 = time.perf_counter()
+        for k in range(n_plain):
+            cx = plain_one(k)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        plain_rate = n_plain / tp
+        out["plain_als_gpu"] = {"value": round(plain_rate, 2), "unit": "submodels/s",
+                                "sample": "%d of %d submodels, %d sweeps each" % (n_plain, K, sweeps),
+                                "speedup_jk_cals": round(value / plain_rate, 2)}
+
+    if not args.no_cpu:
+        print("[bench] CPU oracle on a sample", file=sys.stderr, flush=True)
+        import oracle
+        from threadpoolctl import threadpool_info, threadpool_limits
+        cores = min(16, os.cpu_count() or 1)
+        n_cpu = min(args.cpu_models, K)
+        Th = np.asarray(wl.T)
+        with threadpool_limits(limits=cores):
+            used = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+            t0 = time.perf_counter()
+            oracle.jk_als(Th, 0, wl.ranks, wl.left_out, wl.init, sweeps, models=list(range(n_cpu)))
+            tc = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(n_cpu / tc, 4), "unit": "submodels/s", "cores": int(used),
+                               "kind": "oracle",
+                               "sample": "%d of %d submodels x %d sweeps, numpy float64 per-submodel ALS"
+                                         % (n_cpu, K, sweeps)}
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -189,6 +189,17 @@ int32_t jk_cals_num_tilings(jkc_ctx *ctx);
  * same result up to the order of the float64 sums.  Host only. */
 jkc_status jk_cals_set_tiling(jkc_ctx *ctx, int32_t mode, int32_t variant, int32_t splits);
 
+/* Kernel timing of the fused MTTKRP (the dominant kernel): while enabled,
+ * every MTTKRP launch of this context is bracketed by a pair of HIP events on
+ * the context's stream (at most 65536 launches are kept).  Host only. */
+jkc_status jk_cals_profile(jkc_ctx *ctx, int32_t enable);
+
+/* Synchronise the stream, then report per mode the number of MTTKRP launches
+ * timed since the last read and their summed kernel time in milliseconds
+ * (launches: host [N] int64, ms: host [N] float64; either may be NULL).
+ * Resets the counts. */
+jkc_status jk_cals_profile_read(jkc_ctx *ctx, int64_t *launches, double *ms);
+
 /* Explicit slice removal of Alg. 2: out = T with slice p of the sampled mode
  * deleted (the reduced tensor of a plain per-submodel fit).  Shapes follow
  * prob (dims of the full tensor); out has dims[sampled_mode]-1 in that mode,

@@ -89,6 +89,8 @@ def lib() -> ctypes.CDLL:
         "jk_cals_tune": (I32, [VP, I32]),
         "jk_cals_describe": (ctypes.c_char_p, [VP, I32]),
         "jk_cals_num_tilings": (I32, [VP]),
+        "jk_cals_profile": (I32, [VP, I32]),
+        "jk_cals_profile_read": (I32, [VP, VP, VP]),
         "jk_cals_set_tiling": (I32, [VP, I32, I32, I32]),
         "jk_cals_remove_slice": (I32, [P(Problem), VP, I32, VP]),
         "jk_cals_destroy": (None, [VP]),
@@ -287,6 +289,17 @@ class JkCals:
     def describe(self, mode: int) -> str:
         return lib().jk_cals_describe(self.ctx, int(mode)).decode()
 
+    def profile(self, enable: bool = True):
+        _check(lib().jk_cals_profile(self.ctx, 1 if enable else 0))
+
+    def profile_read(self):
+        """(launches per mode, kernel milliseconds per mode) since last read."""
+        n = np.zeros(self.N, np.int64)
+        ms = np.zeros(self.N, np.float64)
+        _check(lib().jk_cals_profile_read(self.ctx, n.ctypes.data_as(ctypes.c_void_p),
+                                          ms.ctypes.data_as(ctypes.c_void_p)))
+        return n, ms
+
     def num_tilings(self) -> int:
         return int(lib().jk_cals_num_tilings(self.ctx))
 
@@ -343,6 +356,14 @@ def jk_cals_describe(ctx: JkCals, mode: int) -> str:
     return ctx.describe(mode)
 
 
+def jk_cals_profile(ctx: JkCals, enable: bool = True):
+    return ctx.profile(enable)
+
+
+def jk_cals_profile_read(ctx: JkCals):
+    return ctx.profile_read()
+
+
 def jk_cals_num_tilings(ctx: JkCals) -> int:
     return ctx.num_tilings()
 
@@ -373,3 +394,47 @@ def jk_cals_destroy(ctx: JkCals):
 
 def jk_cals_last_error() -> str:
     return lib().jk_cals_last_error().decode()
+
+
+def _make_loss_function():
+    import torch
+
+    class JKCPLoss(torch.autograd.Function):
+        """Per-submodel CP least-squares loss f_k = 1/2 ||T_{-p_k} - [[U^(k)]]||^2
+        over all models of a context, differentiable in the factors.
+
+        forward(ctx, U_0, ..., U_{N-1}) -> loss[K]: installs the factors
+        (device (I_n, C) float64; row p_k of the sampled mode is taken as 0)
+        and runs the all-mode fused MTTKRP, the loss and the gradients in the
+        library.  backward(grad_loss[K]) returns grad_loss[k] * dF_k/dU_n on
+        model k's columns, computed by the library from the cached
+        gradients."""
+
+        @staticmethod
+        def forward(fctx, jkctx, *factors):
+            if len(factors) != jkctx.N:
+                raise ValueError("expected %d factors" % jkctx.N)
+            ones = torch.ones(jkctx.C, dtype=torch.float64, device=jkctx.device)
+            for n, U in enumerate(factors):
+                jkctx.set_factors(n, U.detach().contiguous(), ones)
+            loss = torch.empty(jkctx.K, dtype=torch.float64, device=jkctx.device)
+            jkctx.loss_grad(loss)
+            fctx.jk = jkctx
+            return loss
+
+        @staticmethod
+        def backward(fctx, grad_loss):
+            jkctx = fctx.jk
+            w = grad_loss.detach().to(torch.float64).contiguous()
+            grads = [jkctx.get_grad(n, weights=w) for n in range(jkctx.N)]
+            return (None, *grads)
+
+    return JKCPLoss
+
+
+def __getattr__(name):
+    if name == "JKCPLoss":
+        f = _make_loss_function()
+        globals()["JKCPLoss"] = f
+        return f
+    raise AttributeError(name)

@@ -8,8 +8,13 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
+#include <fstream>
 #include <limits>
+#include <map>
 #include <memory>
+#include <mutex>
+#include <sstream>
 #include <new>
 #include <numeric>
 #include <string>
@@ -44,6 +49,7 @@ jkc_status fail(jkc_status st, const std::string& msg) {
 constexpr int64_t kAlign = 256;
 constexpr int kNumCU = 256;
 constexpr int kSliceChunks = 256;
+constexpr size_t kMaxTimedLaunches = 65536;
 
 int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -190,33 +196,34 @@ Tiling make_tiling(const std::vector<MttkrpVariant>& vars, int v, const ModeShap
   Tiling t;
   const auto& x = vars[v];
   t.variant = v;
-  t.wm = x.wm; t.wn = x.wn; t.tm = x.tm; t.tn = x.tn; t.bk = x.bk;
+  t.wm = x.wm; t.wn = x.wn; t.tm = x.tm; t.tn = x.tn; t.bk = x.bk; t.instr = x.instr;
   t.splits = std::max(1, std::min(splits, s.split_max));
   return t;
 }
 
 int default_splits(const Tiling& t, const ModeShape& s) {
   const int64_t tiles = ((s.M + t.bm() - 1) / t.bm()) * ((s.ncols + t.bn() - 1) / t.bn());
-  const int waves_per_block = t.wm * t.wn;
-  // aim for about two resident waves per SIMD: 2 * 4 * 256 waves
-  const int64_t want_blocks = (2 * 4 * kNumCU) / waves_per_block;
+  // aim for two resident blocks per compute unit
+  const int64_t want_blocks = 2 * kNumCU;
   int64_t s_ = (want_blocks + tiles - 1) / tiles;
-  s_ = std::min<int64_t>(s_, std::max<int64_t>(1, s.J / (4 * t.bk)));
+  s_ = std::min<int64_t>(s_, std::max<int64_t>(1, s.J / (8 * t.bk)));
   return (int)std::max<int64_t>(1, std::min<int64_t>(s_, s.split_max));
 }
 
+// Relative time estimate of a tiling (lower is better): padded matrix-core
+// work, divided by how well one step's MFMA work hides its fixed load/barrier
+// cost and by how well the grid fills the chip, plus split-K partial traffic.
 double model_cost(const Tiling& t, const ModeShape& s) {
   const int64_t mt = (s.M + t.bm() - 1) / t.bm();
   const int64_t nt = (s.ncols + t.bn() - 1) / t.bn();
-  const double padded = (double)mt * t.bm() * nt * t.bn() * (double)s.J;
-  const double waves = (double)mt * nt * t.splits * t.wm * t.wn;
-  const double fill = std::min(1.0, waves / (4.0 * kNumCU));
-  // MFMA time at 128 flop/clk/CU (float64), in arbitrary units
-  double cost = 2.0 * padded / fill;
-  // split-K partial traffic, written and read once (~64 flops per byte)
-  if (t.splits > 1) cost += 64.0 * 2.0 * 8.0 * t.splits * (double)s.M * s.ldc;
-  // re-reads of the tensor per column tile
-  cost += 64.0 * 8.0 * (double)s.M * s.J * nt * 0.25;
+  const double useful = (double)s.M * s.ncols;
+  const double padded = (double)mt * t.bm() * nt * t.bn();
+  const double per_step = (double)t.tm * t.tn * (t.bk / 4) * (t.instr == 1 ? 1.0 : 1.45);
+  const double hide = per_step / (per_step + 6.0);
+  const double blocks = (double)mt * nt * t.splits;
+  const double fill = std::min(1.0, blocks / (2.0 * kNumCU)) * std::min(1.0, (double)(t.wm * t.wn) / 4.0);
+  double cost = (padded / useful) / (hide * std::max(fill, 1e-3));
+  if (t.splits > 1) cost *= 1.0 + 96.0 * t.splits / (double)s.J;
   return cost;
 }
 
@@ -247,9 +254,85 @@ ModeShape mode_shape(const jkc_ctx* ctx, int n, int split_max) {
 
 std::string describe_tiling(const Tiling& t, int precision) {
   char buf[128];
-  snprintf(buf, sizeof(buf), "%s wm%d wn%d tm%d tn%d bk%d s%d", precision ? "bf16x3" : "f64", t.wm,
-           t.wn, t.tm, t.tn, t.bk, t.splits);
+  snprintf(buf, sizeof(buf), "%s v%d wm%d wn%d tm%d tn%d bk%d s%d %s",
+           precision ? "bf16x3" : "f64", t.variant, t.wm, t.wn, t.tm, t.tn, t.bk, t.splits,
+           t.instr == 1 ? "mfma4x4x4" : t.instr == 0 ? "mfma16x16x4" : "mfma16x16x32bf16");
   return buf;
+}
+
+// ---------------------------------------------------------------------------
+// Tuning cache: the tiling jk_cals_tune found for a (precision, shape, mode),
+// kept for the life of the process and, when JKC_TUNE_CACHE names a file,
+// stored there as text ("key|variant geometry|splits" per line).
+// ---------------------------------------------------------------------------
+struct TuneEntry {
+  int wm, wn, tm, tn, bk, instr, splits;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const jkc_ctx* c, int n) {
+  std::ostringstream o;
+  o << "gfx950 p" << c->precision << " f32_" << c->tensor_f32 << " N" << c->N << " d";
+  for (int m = 0; m < c->N; ++m) o << (m ? "x" : "") << c->dims[m];
+  o << " ldc" << c->ldc << " mode" << n;
+  return o.str();
+}
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("JKC_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t a = line.find('|');
+    if (a == std::string::npos) continue;
+    TuneEntry e{};
+    if (sscanf(line.c_str() + a + 1, "%d %d %d %d %d %d|%d", &e.wm, &e.wn, &e.tm, &e.tn, &e.bk,
+               &e.instr, &e.splits) == 7)
+      g_tune[line.substr(0, a)] = e;
+  }
+}
+
+void tune_save_locked() {
+  const char* path = std::getenv("JKC_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::ofstream f(path, std::ios::trunc);
+  for (const auto& kv : g_tune) {
+    const TuneEntry& e = kv.second;
+    f << kv.first << "|" << e.wm << " " << e.wn << " " << e.tm << " " << e.tn << " " << e.bk << " "
+      << e.instr << "|" << e.splits << "\n";
+  }
+}
+
+// Cached tiling for (ctx, mode) if one exists and still names a compiled
+// kernel; returns false otherwise.
+bool tune_lookup(const jkc_ctx* c, int n, const std::vector<MttkrpVariant>& vars,
+                 const ModeShape& shape, Tiling* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  auto it = g_tune.find(tune_key(c, n));
+  if (it == g_tune.end()) return false;
+  const TuneEntry& e = it->second;
+  for (int v = 0; v < (int)vars.size(); ++v) {
+    const auto& x = vars[v];
+    if (x.wm == e.wm && x.wn == e.wn && x.tm == e.tm && x.tn == e.tn && x.bk == e.bk &&
+        x.instr == e.instr) {
+      *out = make_tiling(vars, v, shape, e.splits);
+      return true;
+    }
+  }
+  return false;
+}
+
+void tune_store(const jkc_ctx* c, int n, const Tiling& t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  g_tune[tune_key(c, n)] = TuneEntry{t.wm, t.wn, t.tm, t.tn, t.bk, t.instr, t.splits};
+  tune_save_locked();
 }
 
 // ---------------------------------------------------------------------------
@@ -306,7 +389,28 @@ jkc_status enqueue_mttkrp(jkc_ctx* ctx, int n, const Tiling& t) {
   } else {
     a.partial = ctx->Mbuf;
   }
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (ctx->prof_on && ctx->prof_used < kMaxTimedLaunches) {
+    const size_t i = ctx->prof_used;
+    if (ctx->prof_ev.size() < 2 * (i + 1)) {
+      hipEvent_t a0, a1;
+      JKC_HIP(hipEventCreate(&a0));
+      if (hipEventCreate(&a1) != hipSuccess) {
+        (void)hipEventDestroy(a0);
+        return fail(JKC_EDEVICE, "hipEventCreate failed");
+      }
+      ctx->prof_ev.push_back(a0);
+      ctx->prof_ev.push_back(a1);
+      ctx->prof_mode.push_back(n);
+    }
+    ctx->prof_mode[i] = n;
+    ev0 = ctx->prof_ev[2 * i];
+    ev1 = ctx->prof_ev[2 * i + 1];
+    ++ctx->prof_used;
+    JKC_HIP(hipEventRecord(ev0, ctx->stream));
+  }
   JKC_HIP(vars[t.variant].launch(a, ctx->stream));
+  if (ev1) JKC_HIP(hipEventRecord(ev1, ctx->stream));
   return JKC_OK;
 }
 
@@ -584,7 +688,8 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
   if (vars.empty()) return fail(JKC_EUNSUPPORTED, "no MTTKRP kernels for this precision");
   for (int n = 0; n < pl.N; ++n) {
     c.split_max[n] = pl.split_max[n];
-    c.tiling[n] = choose_tiling(vars, mode_shape(&c, n, pl.split_max[n]));
+    const ModeShape shape = mode_shape(&c, n, pl.split_max[n]);
+    if (!tune_lookup(&c, n, vars, shape, &c.tiling[n])) c.tiling[n] = choose_tiling(vars, shape);
     c.describe[n] = describe_tiling(c.tiling[n], c.precision);
   }
   *out = ctx.release();
@@ -768,6 +873,7 @@ jkc_status jk_cals_tune(jkc_ctx* ctx, int32_t reps) {
     }
     ctx->tiling[n] = best;
     ctx->describe[n] = describe_tiling(best, ctx->precision);
+    if (result == JKC_OK) tune_store(ctx, n, best);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -794,6 +900,33 @@ jkc_status jk_cals_set_tiling(jkc_ctx* ctx, int32_t mode, int32_t variant, int32
   const ModeShape shape = mode_shape(ctx, mode, ctx->split_max[mode]);
   ctx->tiling[mode] = make_tiling(vars, variant, shape, splits);
   ctx->describe[mode] = describe_tiling(ctx->tiling[mode], ctx->precision);
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_profile(jkc_ctx* ctx, int32_t enable) {
+  JKC_TRY(check_ctx(ctx));
+  ctx->prof_on = enable != 0;
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_profile_read(jkc_ctx* ctx, int64_t* launches, double* ms) {
+  JKC_TRY(check_ctx(ctx));
+  JKC_HIP(hipStreamSynchronize(ctx->stream));
+  std::vector<int64_t> cnt(ctx->N, 0);
+  std::vector<double> tot(ctx->N, 0.0);
+  for (size_t i = 0; i < ctx->prof_used; ++i) {
+    float t = 0.f;
+    JKC_HIP(hipEventElapsedTime(&t, ctx->prof_ev[2 * i], ctx->prof_ev[2 * i + 1]));
+    cnt[ctx->prof_mode[i]] += 1;
+    tot[ctx->prof_mode[i]] += t;
+  }
+  ctx->prof_used = 0;
+  for (int n = 0; n < ctx->N; ++n) {
+    if (launches) launches[n] = cnt[n];
+    if (ms) ms[n] = tot[n];
+  }
   g_last_error.clear();
   return JKC_OK;
 }

@@ -30,7 +30,7 @@ constexpr double kPivotTolPerRank = 64.0 * 2.220446049250313e-16;
 // ---------------------------------------------------------------------------
 struct Tiling {
   int variant = -1;   // index into the kernel table (precision specific)
-  int wm = 0, wn = 0, tm = 0, tn = 0, bk = 0;
+  int wm = 0, wn = 0, tm = 0, tn = 0, bk = 0, instr = 0;
   int splits = 1;
   int bm() const { return wm * tm * 16; }
   int bn() const { return wn * tn * 16; }
@@ -59,6 +59,7 @@ struct MttkrpArgs {
 struct MttkrpVariant {
   int wm, wn, tm, tn, bk;
   hipError_t (*launch)(const MttkrpArgs&, hipStream_t);
+  int instr;   // matrix instruction family (kernel specific)
 };
 const std::vector<MttkrpVariant>& mttkrp_f64_variants();
 const std::vector<MttkrpVariant>& mttkrp_split_variants();
@@ -210,6 +211,15 @@ struct jkc_ctx {
   int split_max[jkc::kMaxOrder] = {1, 1, 1, 1};
   std::string describe[jkc::kMaxOrder];
   bool lambda_is_one = true;     // lambda folded into the last factor
+
+  // MTTKRP kernel timing (jk_cals_profile)
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;     // pairs: [2i] start, [2i+1] stop
+  std::vector<int> prof_mode;          // mode of each timed pair
+  size_t prof_used = 0;
+  ~jkc_ctx() {
+    for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
+  }
 
   jkc::ModelTable table() const {
     return jkc::ModelTable{d_off, d_rank, d_left, d_goff, d_order, K};

@@ -15,10 +15,20 @@
 // cleared downstream (Case I).
 //
 // Structure: a block of WM x WN wavefronts owns a BM x BN output tile
-// (BM = WM*TM*16, BN = WN*TN*16) and one contiguous chunk of the K range.
-// Per K step of BK columns it stages the A tile (BM x BK slice of the
-// unfolding) and the generated B tile (BK x BN KRP slice) in LDS; each
-// wavefront then issues TM x TN v_mfma_f64_16x16x4 per 4 columns of K.
+// (BM = WM*TM*16, BN = WN*TN*16) and one contiguous chunk of the K range,
+// walked in steps of BK columns.  Each step is software-pipelined: the
+// global loads of step t+1 (a BM x BK slice of the unfolding and the factor
+// rows of a BK x BN Khatri-Rao slice) are in flight while the matrix cores
+// work on step t out of LDS; the KRP products are formed and written to the
+// other LDS buffer afterwards, so one barrier per step suffices.  Each thread
+// owns one column of the A slice and one column of the B slice and walks its
+// column's multi-index incrementally (no divisions in the loop).
+//
+// Matrix instruction (INSTR):
+//   0: v_mfma_f64_16x16x4 -- one 16x16 tile per instruction;
+//   1: v_mfma_f64_4x4x4 (4 blocks) with the A operand broadcast from block q
+//      (CBSZ = 2, ABID = q): four instructions cover a 16x16x4 step, block b
+//      of the wave producing rows 4q..4q+3 and columns 4b..4b+3.
 // Partials of the K chunks are summed later in a fixed order, so results are
 // bitwise repeatable for a fixed tiling.
 #include "jkc_internal.hpp"
@@ -31,7 +41,52 @@ namespace {
 
 constexpr int kPad = 8;  // LDS row padding (doubles)
 
-template <int WM, int WN, int TM, int TN, int BK>
+// Lane layouts of v_mfma_f64_4x4x4 (4 blocks of 16 lanes); o = lane % 16.
+//   A (4x4, rows i, depth k):   lane offset o = i + 4k
+//   B (depth k, columns j):     lane offset o = j + 4k
+//   D (rows i, columns j):      lane offset o = j + 4i
+__device__ constexpr int l4_a_row(int o) { return o & 3; }
+__device__ constexpr int l4_a_k(int o) { return o >> 2; }
+__device__ constexpr int l4_b_col(int o) { return o & 3; }
+__device__ constexpr int l4_b_k(int o) { return o >> 2; }
+__device__ constexpr int l4_d_row(int o) { return o >> 2; }
+__device__ constexpr int l4_d_col(int o) { return o & 3; }
+
+// Incremental walk over columns j of the unfolding: the multi-index of the
+// other modes (lowest mode fastest, Eq. (3)), the tensor offset of the
+// column and the row offsets into the other modes' multi-factors.
+struct ColWalker {
+  uint32_t idx[kMaxOrder - 1];
+  int64_t j;
+
+  __device__ void init(const MttkrpArgs& a, int64_t j0) {
+    j = j0;
+    uint32_t rem = (uint32_t)min(j0, a.J);
+#pragma unroll
+    for (int q = 0; q < kMaxOrder - 1; ++q) {
+      const uint32_t d = (uint32_t)a.odim[q];
+      idx[q] = rem % d;
+      rem /= d;
+    }
+  }
+  __device__ void advance(const MttkrpArgs& a, int step) {
+    j += step;
+    idx[0] += step;
+    while (idx[0] >= (uint32_t)a.odim[0]) {
+      idx[0] -= a.odim[0];
+      if (++idx[1] >= (uint32_t)a.odim[1]) {
+        idx[1] = 0;
+        ++idx[2];
+      }
+    }
+  }
+  __device__ int64_t toff(const MttkrpArgs& a) const {
+    return (int64_t)idx[0] * a.ostride[0] + (int64_t)idx[1] * a.ostride[1] +
+           (int64_t)idx[2] * a.ostride[2];
+  }
+};
+
+template <int WM, int WN, int TM, int TN, int BK, int INSTR>
 __global__ void __launch_bounds__(64 * WM * WN)
 k_mttkrp_f64(const MttkrpArgs a) {
   constexpr int NT = 64 * WM * WN;
@@ -39,12 +94,15 @@ k_mttkrp_f64(const MttkrpArgs a) {
   constexpr int BN = WN * TN * 16;
   constexpr int LDA = BM + kPad;
   constexpr int LDB = BN + kPad;
-  static_assert(BK % 4 == 0 && BK <= NT, "BK");
+  constexpr int VA = BM * BK / NT;   // A elements per thread per step (one column)
+  constexpr int VB = BN * BK / NT;   // B elements per thread per step (one column)
+  static_assert(BK % 4 == 0, "BK");
+  static_assert(VA >= 1 && VA * NT == BM * BK, "A tile must split evenly over threads");
+  static_assert(VB >= 1 && VB * NT == BN * BK, "B tile must split evenly over threads");
+  static_assert(BM % VA == 0 && BN % VB == 0, "vector width");
 
-  __shared__ double As[BK][LDA];
-  __shared__ double Bs[BK][LDB];
-  __shared__ int64_t s_toff[BK];
-  __shared__ int32_t s_roff[kMaxOrder - 1][BK];
+  __shared__ __attribute__((aligned(16))) double As[2][BK][LDA];
+  __shared__ __attribute__((aligned(16))) double Bs[2][BK][LDB];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -60,6 +118,69 @@ k_mttkrp_f64(const MttkrpArgs a) {
   const int c0 = nt * BN;
   const int64_t kbeg = (int64_t)split * a.kchunk;
   const int64_t kend = min(kbeg + a.kchunk, a.J);
+  const int nsteps = kend > kbeg ? (int)((kend - kbeg + BK - 1) / BK) : 0;
+
+  // Thread roles.  A: mode with unit stride (rows contiguous in memory) ->
+  // threads run along the rows of one column; otherwise along the columns.
+  const bool m_fast = a.stride_n == 1;
+  const int kA = m_fast ? tid / (BM / VA) : tid % BK;
+  const int iA = m_fast ? (tid % (BM / VA)) * VA : (tid / BK) * VA;
+  const int kB = tid % BK;
+  const int cB = (tid / BK) * VB;
+
+  ColWalker wA, wB;
+  wA.init(a, kbeg + kA);
+  wB.init(a, kbeg + kB);
+
+  const double* __restrict__ Tf64 = static_cast<const double*>(a.T);
+  const float* __restrict__ Tf32 = static_cast<const float*>(a.T);
+
+  double ra[VA];
+  double rb[kMaxOrder - 1][VB];
+
+  auto load_step = [&]() {
+    const bool va = wA.j < kend;
+    const int64_t toffA = wA.toff(a);
+#pragma unroll
+    for (int v = 0; v < VA; ++v) {
+      const int row = i0 + iA + v;
+      double x = 0.0;
+      if (va && row < a.M) {
+        const int64_t addr = toffA + (int64_t)row * a.stride_n;
+        x = a.t_is_f32 ? (double)Tf32[addr] : Tf64[addr];
+      }
+      ra[v] = x;
+    }
+    const bool vb = wB.j < kend;
+#pragma unroll
+    for (int q = 0; q < kMaxOrder - 1; ++q) {
+      if (q < a.nother) {
+        const double* __restrict__ urow = a.oU[q] + (int64_t)wB.idx[q] * a.ldc;
+#pragma unroll
+        for (int v = 0; v < VB; ++v) {
+          const int col = c0 + cB + v;
+          rb[q][v] = (vb && col < a.ncols) ? urow[col] : 0.0;
+        }
+      }
+    }
+  };
+  auto store_step = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < VA; ++v) As[buf][kA][iA + v] = ra[v];
+#pragma unroll
+    for (int v = 0; v < VB; ++v) {
+      // product from the highest mode down (the listing order of Eq. (1))
+      double x = 0.0;
+      bool first = true;
+#pragma unroll
+      for (int q = kMaxOrder - 2; q >= 0; --q)
+        if (q < a.nother) {
+          x = first ? rb[q][v] : x * rb[q][v];
+          first = false;
+        }
+      Bs[buf][kB][cB + v] = x;
+    }
+  };
 
   v4d acc[TM][TN];
 #pragma unroll
@@ -67,93 +188,60 @@ k_mttkrp_f64(const MttkrpArgs a) {
 #pragma unroll
     for (int y = 0; y < TN; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  const double* __restrict__ Tf64 = static_cast<const double*>(a.T);
-  const float* __restrict__ Tf32 = static_cast<const float*>(a.T);
+  if (nsteps > 0) {
+    load_step();
+    store_step(0);
+  }
+  __syncthreads();
 
-  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-    // Column decode: j -> indices of the other modes (lowest fastest, Eq. (3)).
-    if (tid < BK) {
-      const int64_t j = k0 + tid;
-      if (j < kend) {
-        uint32_t rem = (uint32_t)j;
-        int64_t toff = 0;
-#pragma unroll
-        for (int q = 0; q < kMaxOrder - 1; ++q) {
-          if (q < a.nother) {
-            const uint32_t d = (uint32_t)a.odim[q];
-            const uint32_t idx = rem % d;
-            rem /= d;
-            toff += (int64_t)idx * a.ostride[q];
-            s_roff[q][tid] = (int32_t)idx * a.ldc;
-          }
-        }
-        s_toff[tid] = toff;
-      } else {
-        s_toff[tid] = -1;
-      }
+  const int o16 = lane & 15;
+  const int blk = lane >> 4;
+  for (int s = 0; s < nsteps; ++s) {
+    const int buf = s & 1;
+    const bool more = s + 1 < nsteps;
+    if (more) {
+      wA.advance(a, BK);
+      wB.advance(a, BK);
+      load_step();
     }
-    __syncthreads();
-
-    // A tile: As[k][i] = T_(n)(i0 + i, k0 + k), zero outside the matrix.
-    if (a.stride_n == 1) {
-      for (int e = tid; e < BM * BK; e += NT) {
-        const int i = e % BM, k = e / BM;
-        const int64_t toff = s_toff[k];
-        double v = 0.0;
-        if (toff >= 0 && i0 + i < a.M) {
-          const int64_t addr = toff + (int64_t)(i0 + i);
-          v = a.t_is_f32 ? (double)Tf32[addr] : Tf64[addr];
-        }
-        As[k][i] = v;
-      }
-    } else {
-      for (int e = tid; e < BM * BK; e += NT) {
-        const int k = e % BK, i = e / BK;
-        const int64_t toff = s_toff[k];
-        double v = 0.0;
-        if (toff >= 0 && i0 + i < a.M) {
-          const int64_t addr = toff + (int64_t)(i0 + i) * a.stride_n;
-          v = a.t_is_f32 ? (double)Tf32[addr] : Tf64[addr];
-        }
-        As[k][i] = v;
-      }
-    }
-    // B tile: Bs[k][c] = KRP(k0 + k, c0 + c), multiplied from the highest
-    // mode down (the listing order of Eq. (1)).
-    for (int e = tid; e < BK * BN; e += NT) {
-      const int c = e % BN, k = e / BN;
-      const int col = c0 + c;
-      double v = 0.0;
-      if (s_toff[k] >= 0 && col < a.ncols) {
-        const int q0 = a.nother - 1;
-        v = a.oU[q0][s_roff[q0][k] + col];
-        for (int q = q0 - 1; q >= 0; --q) v *= a.oU[q][s_roff[q][k] + col];
-      }
-      Bs[k][c] = v;
-    }
-    __syncthreads();
-
-    const int arow = wm * TM * 16 + (lane & 15);
-    const int bcol = wn * TN * 16 + (lane & 15);
-    const int kq = lane >> 4;
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       double av[TM], bv[TN];
+      if (INSTR == 0) {
 #pragma unroll
-      for (int x = 0; x < TM; ++x) av[x] = As[kk + kq][arow + x * 16];
+        for (int x = 0; x < TM; ++x) av[x] = As[buf][kk + blk][wm * TM * 16 + x * 16 + o16];
 #pragma unroll
-      for (int y = 0; y < TN; ++y) bv[y] = Bs[kk + kq][bcol + y * 16];
+        for (int y = 0; y < TN; ++y) bv[y] = Bs[buf][kk + blk][wn * TN * 16 + y * 16 + o16];
 #pragma unroll
-      for (int x = 0; x < TM; ++x)
+        for (int x = 0; x < TM; ++x)
+#pragma unroll
+          for (int y = 0; y < TN; ++y)
+            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int x = 0; x < TM; ++x)
+          av[x] = As[buf][kk + l4_a_k(o16)][wm * TM * 16 + x * 16 + 4 * blk + l4_a_row(o16)];
 #pragma unroll
         for (int y = 0; y < TN; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
+          bv[y] = Bs[buf][kk + l4_b_k(o16)][wn * TN * 16 + y * 16 + 4 * blk + l4_b_col(o16)];
+#pragma unroll
+        for (int x = 0; x < TM; ++x)
+#pragma unroll
+          for (int y = 0; y < TN; ++y) {
+            acc[x][y][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[x], bv[y], acc[x][y][0], 2, 0, 0);
+            acc[x][y][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[x], bv[y], acc[x][y][1], 2, 1, 0);
+            acc[x][y][2] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[x], bv[y], acc[x][y][2], 2, 2, 0);
+            acc[x][y][3] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[x], bv[y], acc[x][y][3], 2, 3, 0);
+          }
+      }
     }
+    if (more) store_step(buf ^ 1);
     __syncthreads();
   }
 
-  // Epilogue: for v_mfma_f64_16x16x4 lane l holds, in accumulator element r,
-  // row 4*r + l/16 and column l%16 of its 16x16 tile.
+  // Epilogue.  16x16x4: lane l holds, in element r, row 4*r + l/16 and
+  // column l%16 of its tile.  4x4x4 broadcast: element q holds row
+  // 4*q + (D row of o16) and column 4*(l/16) + (D column of o16).
   double* __restrict__ out = a.partial + (int64_t)split * a.M * a.ldc;
 #pragma unroll
   for (int x = 0; x < TM; ++x)
@@ -161,32 +249,42 @@ k_mttkrp_f64(const MttkrpArgs a) {
     for (int y = 0; y < TN; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = i0 + wm * TM * 16 + x * 16 + 4 * r + (lane >> 4);
-        const int col = c0 + wn * TN * 16 + y * 16 + (lane & 15);
+        int rr, cc;
+        if (INSTR == 0) {
+          rr = 4 * r + blk;
+          cc = o16;
+        } else {
+          rr = 4 * r + l4_d_row(o16);
+          cc = 4 * blk + l4_d_col(o16);
+        }
+        const int row = i0 + wm * TM * 16 + x * 16 + rr;
+        const int col = c0 + wn * TN * 16 + y * 16 + cc;
         if (row < a.M && col < a.ldc) out[(int64_t)row * a.ldc + col] = acc[x][y][r];
       }
 }
 
-template <int WM, int WN, int TM, int TN, int BK>
+template <int WM, int WN, int TM, int TN, int BK, int INSTR>
 hipError_t launch_f64(const MttkrpArgs& a, hipStream_t s) {
   dim3 grid(a.mtiles * a.ntiles, a.splits);
-  hipLaunchKernelGGL((k_mttkrp_f64<WM, WN, TM, TN, BK>), grid, dim3(64 * WM * WN), 0, s, a);
+  hipLaunchKernelGGL((k_mttkrp_f64<WM, WN, TM, TN, BK, INSTR>), grid, dim3(64 * WM * WN), 0, s, a);
   return hipGetLastError();
 }
+
+#define JKC_F64_VARIANT(WM, WN, TM, TN, BK, I) \
+  { WM, WN, TM, TN, BK, &launch_f64<WM, WN, TM, TN, BK, I>, I }
 
 }  // namespace
 
 const std::vector<MttkrpVariant>& mttkrp_f64_variants() {
   static const std::vector<MttkrpVariant> v = {
-      {2, 2, 2, 2, 16, &launch_f64<2, 2, 2, 2, 16>},   // 64 x 64
-      {2, 2, 2, 4, 16, &launch_f64<2, 2, 2, 4, 16>},   // 64 x 128
-      {1, 4, 4, 2, 16, &launch_f64<1, 4, 4, 2, 16>},   // 64 x 128
-      {1, 4, 7, 2, 16, &launch_f64<1, 4, 7, 2, 16>},   // 112 x 128
-      {2, 2, 4, 2, 16, &launch_f64<2, 2, 4, 2, 16>},   // 128 x 64
-      {2, 2, 1, 1, 32, &launch_f64<2, 2, 1, 1, 32>},   // 32 x 32
-      {4, 1, 1, 1, 32, &launch_f64<4, 1, 1, 1, 32>},   // 64 x 16
-      {4, 1, 2, 1, 32, &launch_f64<4, 1, 2, 1, 32>},   // 128 x 16
-      {1, 4, 1, 1, 32, &launch_f64<1, 4, 1, 1, 32>},   // 16 x 64
+      JKC_F64_VARIANT(2, 2, 2, 2, 16, 0),   // 64 x 64
+      JKC_F64_VARIANT(2, 2, 2, 4, 16, 0),   // 64 x 128
+      JKC_F64_VARIANT(2, 2, 4, 2, 16, 0),   // 128 x 64
+      JKC_F64_VARIANT(1, 4, 7, 2, 16, 0),   // 112 x 128
+      JKC_F64_VARIANT(2, 2, 4, 4, 16, 0),   // 128 x 128
+      JKC_F64_VARIANT(2, 2, 1, 1, 32, 0),   // 32 x 32
+      JKC_F64_VARIANT(4, 1, 1, 1, 32, 0),   // 64 x 16
+      JKC_F64_VARIANT(4, 1, 2, 1, 32, 0),   // 128 x 16
   };
   return v;
 }

@@ -1,0 +1,115 @@
+"""The CP loss gradient (an all-mode fused MTTKRP) behind
+torch.autograd.Function: against the oracle gradient on the explicitly
+reduced tensors, against central finite differences (h = 1e-3), the
+vanishing gradient right after an ALS update, and gradient refinement."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_2112_03985_amd as jk
+from gpu_util import make_ctx, rel, say, to_np, cols
+
+pytestmark = pytest.mark.gpu
+
+
+def _reduced(wl, k, facs):
+    c = cols(wl, k)
+    U = [np.array(f[:, c], dtype=np.float64) for f in facs]
+    p = int(wl.left_out[k])
+    U[wl.sampled_mode] = oracle.reduce_init(U[wl.sampled_mode], p)
+    Tk = oracle.reduce_tensor(np.asarray(wl.T, dtype=np.float64), wl.sampled_mode, p)
+    return Tk, U, p
+
+
+@pytest.mark.parametrize("seed,dims,ranks,lo", [
+    (41, (14, 11, 9), [3, 2, 4], [-1, 0, 13]),
+    (42, (8, 7, 6, 5), [2, 3], [7, -1]),
+])
+def test_loss_and_gradient_match_oracle(seed, dims, ranks, lo):
+    import torch
+    wl = synth.random_problem(seed, dims, ranks, lo, noise=0.2)
+    say("grad parity", seed)
+    ctx = make_ctx(wl)
+    facs = [torch.from_numpy(u).cuda() for u in wl.init]
+    loss = jk.JKCPLoss.apply(ctx, *facs)
+    w = torch.linspace(0.5, 2.0, wl.K, dtype=torch.float64, device="cuda")
+    grads = torch.autograd.grad((loss * w).sum(), facs)
+    L = to_np(loss)
+    G = [to_np(g) for g in grads]
+    wn = to_np(w)
+    for k in range(wl.K):
+        Tk, U, p = _reduced(wl, k, wl.init)
+        f, g = oracle.loss_and_grad(Tk, U)
+        assert abs(L[k] - f) <= 1e-11 * max(1.0, 0.5 * np.sum(Tk ** 2)), (k, L[k], f)
+        for n in range(len(dims)):
+            gn = g[n] * wn[k]
+            if n == wl.sampled_mode and p >= 0:
+                gn = np.insert(gn, p, 0.0, axis=0)
+            assert rel(G[n][:, cols(wl, k)], gn) <= 1e-11, (k, n)
+
+
+def test_gradient_matches_central_differences():
+    """Central differences of the library's own loss at h = 1e-3 (f is
+    quadratic in each entry, so the difference quotient is exact up to
+    rounding)."""
+    import torch
+    wl = synth.random_problem(43, (9, 8, 7), [2, 3], [-1, 4], noise=0.3)
+    ctx = make_ctx(wl)
+    base = [torch.from_numpy(u).cuda() for u in wl.init]
+    base[0][4, 2:5] = 0.0  # the left-out row of model 1 is not a parameter
+    loss = torch.empty(wl.K, dtype=torch.float64, device="cuda")
+    facs = [b.clone() for b in base]
+    Lt = jk.JKCPLoss.apply(ctx, *facs)
+    grads = [to_np(x) for x in torch.autograd.grad(Lt.sum(), facs)]
+    h = 1e-3
+    rng = np.random.default_rng(0)
+    for _ in range(12):
+        n = int(rng.integers(3))
+        i = int(rng.integers(wl.dims[n]))
+        c = int(rng.integers(wl.C))
+        if n == 0 and i == 4 and 2 <= c < 5:
+            continue
+        vals = []
+        for sgn in (1, -1):
+            f2 = [b.clone() for b in base]
+            f2[n][i, c] += sgn * h
+            vals.append(to_np(jk.JKCPLoss.apply(ctx, *f2)).sum())
+        fd = (vals[0] - vals[1]) / (2 * h)
+        scale = max(1.0, abs(grads[n][i, c]))
+        assert abs(fd - grads[n][i, c]) <= 1e-6 * scale * max(1.0, np.sum(wl.T ** 2) * 1e-3), (n, i, c)
+
+
+def test_gradient_vanishes_for_the_last_updated_mode():
+    wl = synth.random_problem(44, (12, 10, 8), [3, 3], [-1, 5], noise=0.1)
+    ctx = make_ctx(wl)
+    ctx.sweep(3)
+    import torch
+    loss = torch.empty(wl.K, dtype=torch.float64, device="cuda")
+    ctx.loss_grad(loss)
+    g_last = to_np(ctx.get_grad(2))
+    g_first = to_np(ctx.get_grad(0))
+    U2 = to_np(ctx.get_factors(2)[0])
+    assert np.linalg.norm(g_last) <= 1e-10 * max(1.0, np.linalg.norm(U2)) * np.sum(wl.T ** 2) ** 0.5
+    assert np.linalg.norm(g_first) > 1e-8
+
+
+def test_refinement_matches_oracle():
+    """Gradient refinement (reading: fixed step 1 / sum_n ||H_n||_F taken at
+    the first step, all modes at once) after a few ALS sweeps, sampled
+    models, against the oracle running the same rule."""
+    wl = synth.random_problem(45, (15, 12, 10), [3, 3, 2], [-1, 7, 14], noise=0.05)
+    sweeps, steps = 4, 25
+    ctx = make_ctx(wl)
+    ctx.sweep(sweeps)
+    ctx.refine(steps)
+    facs = [to_np(ctx.get_factors(n)[0]) for n in range(3)]
+    res = oracle.jk_als(np.asarray(wl.T), 0, wl.ranks, wl.left_out, wl.init, sweeps)
+    for k, r in res.items():
+        U = [u.copy() for u in r.U]
+        U[-1] = U[-1] * r.lam[None, :]
+        Tk = oracle.reduce_tensor(np.asarray(wl.T), 0, int(wl.left_out[k]))
+        Ur = oracle.gd_refine(Tk, U, steps)
+        Up = r.padded(Ur)
+        for n in range(3):
+            assert rel(facs[n][:, cols(wl, k)], Up[n]) <= 1e-10, (k, n)
