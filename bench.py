@@ -24,6 +24,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense float64 matrix peak (datasheet)
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense bfloat16 matrix peak (datasheet)
 
 
 def parse():
@@ -37,6 +38,10 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-submodel GPU baseline")
     ap.add_argument("--plain-models", type=int, default=10)
     ap.add_argument("--cpu-models", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
+                    help="c2: the benchmark workload (default); c3/c4: the uneven-batch and "
+                         "split-precision workloads, for kernel measurements")
+    ap.add_argument("--precision", default=None, choices=["fp64", "bf16x3", "bf16x6"])
     return ap.parse_args()
 
 
@@ -56,22 +61,42 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
-    wl = synth.config2()
+    if args.workload == "c2":
+        wl = synth.config2()
+        desc_w = ("c2: 100x200x200 f64 fluorescence-like tensor, rank 5, 2% noise; "
+                  "100 leave-one-out submodels of rank 5; %d ALS sweeps")
+        prec_name = args.precision or "fp64"
+    elif args.workload == "c3":
+        wl = synth.config3()
+        desc_w = ("c3: 300x250x200 f64 rank-8 tensor; ranks 1..10 x 5 inits x 300 leave-one-out "
+                  "= 15000 submodels (C = 82500); %d ALS sweeps")
+        prec_name = args.precision or "fp64"
+    else:
+        wl = synth.config4()
+        desc_w = ("c4: 200x120x100x80 f64 rank-12 tensor, 1% noise; 200 leave-one-out submodels "
+                  "of rank 12; split-precision MTTKRP; %d ALS sweeps")
+        prec_name = args.precision or "bf16x3"
+    precision = {"fp64": jk.JKC_FP64, "bf16x3": jk.JKC_SPLIT_BF16X3,
+                 "bf16x6": jk.JKC_SPLIT_BF16X6}[prec_name]
     K, C, P = wl.K, wl.C, int(np.prod(wl.dims))
+    N = len(wl.dims)
     sweeps = args.sweeps
+    if args.workload != "c2":
+        args.no_plain = True
+        args.no_cpu = True
     T = jk.to_device_tensor(wl.T)
     init = [torch.from_numpy(np.ascontiguousarray(u)).cuda() for u in wl.init]
     torch.cuda.synchronize()
 
     tiling = None
     if args.tune:
-        ctx = jk.JkCals(T, wl.dims, 0, wl.ranks, wl.left_out, init)
+        ctx = jk.JkCals(T, wl.dims, 0, wl.ranks, wl.left_out, init, precision=precision)
         ctx.tune(5)
-        tiling = [ctx.describe(n) for n in range(3)]
+        tiling = [ctx.describe(n) for n in range(N)]
         del ctx
 
     def step(profile=False):
-        ctx = jk.JkCals(T, wl.dims, 0, wl.ranks, wl.left_out, init)
+        ctx = jk.JkCals(T, wl.dims, 0, wl.ranks, wl.left_out, init, precision=precision)
         if profile:
             ctx.profile(True)
         ctx.sweep(sweeps)
@@ -81,12 +106,12 @@ def main():
     for _ in range(args.warmup):
         c = step()
     torch.cuda.synchronize()
-    desc = [c.describe(n) for n in range(3)]
+    desc = [c.describe(n) for n in range(N)]
     del c
 
     print("[bench] timing %d steps" % args.steps, file=sys.stderr, flush=True)
-    launches = np.zeros(3, np.int64)
-    kms = np.zeros(3)
+    launches = np.zeros(N, np.int64)
+    kms = np.zeros(N)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -107,20 +132,26 @@ def main():
     flops_per_launch = 2.0 * C * P          # fused MTTKRP of one mode (Sec. 4.2)
     avg_ms = float(kms.sum() / max(launches.sum(), 1))
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
-                "kernel": "k_mttkrp_f64", "avg_launch_ms": round(avg_ms, 5),
-                "per_mode_avg_ms": [round(float(kms[n] / max(launches[n], 1)), 5) for n in range(3)],
-                "flops_per_launch": flops_per_launch}
+    if precision == jk.JKC_FP64:
+        peak, kname, issued = PEAK_FP64_TFLOPS, "k_mttkrp_f64", 1.0
+    else:
+        # bf16 matrix peak, counting the bf16 flops actually issued
+        issued = 3.0 if precision == jk.JKC_SPLIT_BF16X3 else 6.0
+        peak, kname = PEAK_BF16_TFLOPS, "k_mttkrp_split"
+    roofline = {"bound": "mfma", "achieved": round(achieved * issued, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved * issued / peak, 4), "traffic": None,
+                "kernel": kname, "avg_launch_ms": round(avg_ms, 5),
+                "per_mode_avg_ms": [round(float(kms[n] / max(launches[n], 1)), 5) for n in range(N)],
+                "flops_per_launch": flops_per_launch * issued}
 
-    out = {"metric": "jackknife submodels fitted/sec (JK-CALS, 100 sweeps each)",
+    out = {"metric": "jackknife submodels fitted/sec (JK-CALS, %d sweeps each)" % sweeps,
            "value": round(value, 2), "unit": "submodels/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if precision == jk.JKC_FP64 else "bf16x%d+f32acc+f64" % (3 if precision == 1 else 6),
            "data": "synthetic",
-           "config": {"workload": "c2: 100x200x200 f64 fluorescence-like tensor, rank 5, 2% noise; "
-                                  "100 leave-one-out submodels of rank 5; 100 ALS sweeps",
-                      "dims": list(wl.dims), "models": K, "rank": 5, "columns": C, "sweeps": sweeps,
+           "config": {"workload": desc_w % sweeps, "dims": list(wl.dims), "models": K,
+                      "columns": C, "sweeps": sweeps, "precision": prec_name,
                       "tiling": tiling or desc},
            "mttkrp_tflops": round(achieved, 3),
            "roofline": roofline,

@@ -66,10 +66,17 @@ typedef enum {
 
 typedef enum {
   JKC_FP64 = 0,           /* MTTKRP in float64 MFMA, float64 accumulation    */
-  JKC_SPLIT_BF16X3 = 1    /* MTTKRP as three bfloat16 MFMA products
-                             (hi*hi + hi*lo + lo*hi) with float32
-                             accumulation flushed to float64; everything
-                             else in float64                                */
+  JKC_SPLIT_BF16X3 = 1,   /* MTTKRP with each operand split into two
+                             bfloat16 terms and three MFMA products
+                             (hi*hi + hi*lo + lo*hi), float32 accumulation
+                             flushed to float64; everything else float64.
+                             ~2^-17 relative per product: normwise MTTKRP
+                             error a few 1e-6, up to ~1e-5 when the sums
+                             cancel strongly                                */
+  JKC_SPLIT_BF16X6 = 2    /* three bfloat16 terms per operand, the six
+                             products down to 2^-16 magnitude: ~2^-23
+                             relative per product; 2x the MFMA work of
+                             JKC_SPLIT_BF16X3                               */
 } jkc_precision;
 
 typedef enum { JKC_TENSOR_F64 = 0, JKC_TENSOR_F32 = 1 } jkc_tensor_dtype;
@@ -89,7 +96,7 @@ typedef struct {
   int32_t tensor_dtype;        /* jkc_tensor_dtype                            */
   int32_t precision;           /* jkc_precision                               */
   int32_t copy_tensor;         /* 1: copy T into the workspace; 0: use in place
-                                  (FP64 precision only)                       */
+                                  (JKC_FP64 only)                             */
   void *stream;                /* hipStream_t, NULL = default stream          */
 } jkc_problem;
 
@@ -105,7 +112,7 @@ jkc_status jk_cals_workspace_size(const jkc_problem *prob, size_t *bytes);
  *   workspace : device, >= jk_cals_workspace_size bytes, 256-byte aligned.
  *   out    : receives the context.  Owned by the caller; free with
  *            jk_cals_destroy.
- * Enqueues the tensor copy (or bf16 hi/lo split), the slice norms
+ * Enqueues the tensor copy (or bfloat16 split), the slice norms
  * ||T_{-p}||^2 used by the submodel error (Alg. 3, error step), factor
  * packing and the initial Gram matrices.  Asynchronous on the stream. */
 jkc_status jk_cals_init(const jkc_problem *prob, const void *tensor,
@@ -179,6 +186,12 @@ jkc_status jk_cals_tune(jkc_ctx *ctx, int32_t reps);
 
 /* The current tiling of `mode` as text, e.g. "f64 wm2 wn2 tm2 tn2 bk16 s8". */
 const char *jk_cals_describe(jkc_ctx *ctx, int32_t mode);
+
+/* Choose the per-model update kernel: 0 = one wavefront per model with the
+ * model's rows in LDS whenever they fit (default), 1 = one 256-thread block
+ * per model.  Both compute the same update with the same summation order
+ * for U, lambda and the Gram matrices.  Host only. */
+jkc_status jk_cals_set_update_kernel(jkc_ctx *ctx, int32_t which);
 
 /* Number of MTTKRP tilings compiled for the context's precision (0 if ctx is
  * NULL). */

@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(_HERE, "libjkcals.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "jk_cals.h")
 
 JKC_OK, JKC_EINVAL, JKC_ENOMEM, JKC_EDEVICE, JKC_ESTATE, JKC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-JKC_FP64, JKC_SPLIT_BF16X3 = 0, 1
+JKC_FP64, JKC_SPLIT_BF16X3, JKC_SPLIT_BF16X6 = 0, 1, 2
 JKC_TENSOR_F64, JKC_TENSOR_F32 = 0, 1
 JKC_ST_CONVERGED, JKC_ST_FALLBACK, JKC_ST_NONFINITE = 1, 2, 4
 MAX_RANK = 32
@@ -89,6 +89,7 @@ def lib() -> ctypes.CDLL:
         "jk_cals_tune": (I32, [VP, I32]),
         "jk_cals_describe": (ctypes.c_char_p, [VP, I32]),
         "jk_cals_num_tilings": (I32, [VP]),
+        "jk_cals_set_update_kernel": (I32, [VP, I32]),
         "jk_cals_profile": (I32, [VP, I32]),
         "jk_cals_profile_read": (I32, [VP, VP, VP]),
         "jk_cals_set_tiling": (I32, [VP, I32, I32, I32]),
@@ -300,6 +301,9 @@ class JkCals:
                                           ms.ctypes.data_as(ctypes.c_void_p)))
         return n, ms
 
+    def set_update_kernel(self, which: int):
+        _check(lib().jk_cals_set_update_kernel(self.ctx, int(which)))
+
     def num_tilings(self) -> int:
         return int(lib().jk_cals_num_tilings(self.ctx))
 
@@ -362,6 +366,10 @@ def jk_cals_profile(ctx: JkCals, enable: bool = True):
 
 def jk_cals_profile_read(ctx: JkCals):
     return ctx.profile_read()
+
+
+def jk_cals_set_update_kernel(ctx: JkCals, which: int):
+    return ctx.set_update_kernel(which)
 
 
 def jk_cals_num_tilings(ctx: JkCals) -> int:

@@ -76,6 +76,8 @@ struct Plan {
     int64_t tbytes = 0;
     if (precision == JKC_SPLIT_BF16X3)
       tbytes = 2 * P * 2;
+    else if (precision == JKC_SPLIT_BF16X6)
+      tbytes = 3 * P * 2;
     else if (copy_tensor)
       tbytes = P * es;
     items.push_back({"tensor", tbytes});
@@ -162,8 +164,9 @@ jkc_status make_plan(const jkc_problem* prob, Plan* pl) {
   if (prob->tensor_dtype != JKC_TENSOR_F64 && prob->tensor_dtype != JKC_TENSOR_F32)
     return fail(JKC_EINVAL, "tensor_dtype must be 0 (f64) or 1 (f32)");
   pl->tensor_f32 = prob->tensor_dtype == JKC_TENSOR_F32;
-  if (prob->precision != JKC_FP64 && prob->precision != JKC_SPLIT_BF16X3)
-    return fail(JKC_EINVAL, "precision must be 0 (fp64) or 1 (split bf16x3)");
+  if (prob->precision != JKC_FP64 && prob->precision != JKC_SPLIT_BF16X3 &&
+      prob->precision != JKC_SPLIT_BF16X6)
+    return fail(JKC_EINVAL, "precision must be 0 (fp64), 1 (split bf16x3) or 2 (split bf16x6)");
   pl->precision = prob->precision;
   if (prob->copy_tensor != 0 && prob->copy_tensor != 1)
     return fail(JKC_EINVAL, "copy_tensor must be 0 or 1");
@@ -255,7 +258,8 @@ ModeShape mode_shape(const jkc_ctx* ctx, int n, int split_max) {
 std::string describe_tiling(const Tiling& t, int precision) {
   char buf[128];
   snprintf(buf, sizeof(buf), "%s v%d wm%d wn%d tm%d tn%d bk%d s%d %s",
-           precision ? "bf16x3" : "f64", t.variant, t.wm, t.wn, t.tm, t.tn, t.bk, t.splits,
+           precision == JKC_SPLIT_BF16X3 ? "bf16x3" : precision == JKC_SPLIT_BF16X6 ? "bf16x6" : "f64",
+           t.variant, t.wm, t.wn, t.tm, t.tn, t.bk, t.splits,
            t.instr == 1 ? "mfma4x4x4" : t.instr == 0 ? "mfma16x16x4" : "mfma16x16x32bf16");
   return buf;
 }
@@ -339,7 +343,9 @@ void tune_store(const jkc_ctx* c, int n, const Tiling& t) {
 // Launch helpers.
 // ---------------------------------------------------------------------------
 const std::vector<MttkrpVariant>& variants_for(const jkc_ctx* ctx) {
-  return ctx->precision == JKC_SPLIT_BF16X3 ? mttkrp_split_variants() : mttkrp_f64_variants();
+  if (ctx->precision == JKC_SPLIT_BF16X3) return mttkrp_split_variants();
+  if (ctx->precision == JKC_SPLIT_BF16X6) return mttkrp_split3_variants();
+  return mttkrp_f64_variants();
 }
 
 // Enqueue the fused MTTKRP of mode n.  Result: split-K partials in
@@ -348,12 +354,12 @@ jkc_status enqueue_mttkrp(jkc_ctx* ctx, int n, const Tiling& t) {
   const auto& vars = variants_for(ctx);
   if (t.variant < 0 || t.variant >= (int)vars.size()) return fail(JKC_ESTATE, "no tiling");
   MttkrpArgs a{};
-  if (ctx->precision == JKC_SPLIT_BF16X3) {
-    a.T = ctx->T_hi;
-    a.T_lo = ctx->T_lo;
+  if (ctx->nterm > 0) {
+    a.T = ctx->T_planes;
+    a.plane = ctx->P;
   } else {
     a.T = ctx->T;
-    a.T_lo = nullptr;
+    a.plane = 0;
   }
   a.t_is_f32 = ctx->tensor_f32;
   int q = 0;
@@ -457,6 +463,13 @@ jkc_status enqueue_update(jkc_ctx* ctx, int n, double tol, int check_conv) {
   a.last_mode = (n == ctx->N - 1) ? 1 : 0;
   a.tol = tol;
   a.check_conv = check_conv;
+  a.rmax = ctx->rmax;
+  // wavefront-per-model kernel when a model's rows fit in 64 KB of LDS with
+  // at least one wavefront per block
+  const int64_t per_wave = update_wave_lds_doubles(ctx->rmax, (int)ctx->dims[n]) * 8;
+  const int64_t budget = 64 * 1024;
+  a.waves_per_block = (int32_t)std::min<int64_t>(4, budget / per_wave);
+  a.wave_lds_doubles = a.waves_per_block > 0 && ctx->wave_update ? per_wave / 8 : 0;
   JKC_HIP(launch_update(a, ctx->stream));
   return JKC_OK;
 }
@@ -580,6 +593,9 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
   c.stream = static_cast<hipStream_t>(prob->stream);
   c.gsize = pl.gsize;
   c.partial_doubles = pl.partial_doubles;
+  c.maxI = pl.maxI;
+  c.rmax = 0;
+  for (int k = 0; k < pl.K; ++k) c.rmax = std::max(c.rmax, prob->ranks[k]);
   c.h_rank.assign(prob->ranks, prob->ranks + pl.K);
   c.h_left.assign(prob->left_out, prob->left_out + pl.K);
   c.h_off.resize(pl.K);
@@ -649,10 +665,10 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
   JKC_HIP(hipMemcpyAsync(c.d_colmodel, c.h_colmodel.data(), pl.ldc * 4, hipMemcpyHostToDevice, st));
 
   // tensor residency
-  if (pl.precision == JKC_SPLIT_BF16X3) {
-    c.T_hi = static_cast<uint16_t*>(tbuf);
-    c.T_lo = c.T_hi + pl.P;
-    JKC_HIP(launch_split_tensor(tensor, pl.tensor_f32, c.T_hi, c.T_lo, pl.P, st));
+  if (pl.precision != JKC_FP64) {
+    c.nterm = pl.precision == JKC_SPLIT_BF16X6 ? 3 : 2;
+    c.T_planes = static_cast<uint16_t*>(tbuf);
+    JKC_HIP(launch_split_tensor(tensor, pl.tensor_f32, c.T_planes, c.nterm, pl.P, st));
   } else if (pl.copy_tensor) {
     JKC_HIP(launch_copy_tensor(tensor, pl.tensor_f32, tbuf, pl.P, st));
     c.T = tbuf;
@@ -884,6 +900,14 @@ jkc_status jk_cals_tune(jkc_ctx* ctx, int32_t reps) {
 const char* jk_cals_describe(jkc_ctx* ctx, int32_t mode) {
   if (!ctx || mode < 0 || mode >= ctx->N) return "";
   return ctx->describe[mode].c_str();
+}
+
+jkc_status jk_cals_set_update_kernel(jkc_ctx* ctx, int32_t which) {
+  JKC_TRY(check_ctx(ctx));
+  if (which != 0 && which != 1) return fail(JKC_EINVAL, "which must be 0 or 1");
+  ctx->wave_update = which == 0;
+  g_last_error.clear();
+  return JKC_OK;
 }
 
 int32_t jk_cals_num_tilings(jkc_ctx* ctx) {

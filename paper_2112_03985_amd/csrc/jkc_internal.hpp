@@ -37,8 +37,8 @@ struct Tiling {
 };
 
 struct MttkrpArgs {
-  const void* T;            // tensor (f64/f32) or bf16 hi plane (split path)
-  const void* T_lo;         // bf16 lo plane (split path only)
+  const void* T;            // tensor (f64/f32), or the first bf16 plane (split paths)
+  int64_t plane;            // split paths: elements between bf16 planes
   int32_t t_is_f32;         // FP64 path: tensor stored as float32
   const double* oU[kMaxOrder - 1];   // factors of the other modes, ascending
   int32_t odim[kMaxOrder - 1];       // their sizes
@@ -62,7 +62,8 @@ struct MttkrpVariant {
   int instr;   // matrix instruction family (kernel specific)
 };
 const std::vector<MttkrpVariant>& mttkrp_f64_variants();
-const std::vector<MttkrpVariant>& mttkrp_split_variants();
+const std::vector<MttkrpVariant>& mttkrp_split_variants();    // two bf16 terms
+const std::vector<MttkrpVariant>& mttkrp_split3_variants();   // three bf16 terms
 
 // ---------------------------------------------------------------------------
 // Per-model batched kernels.
@@ -96,8 +97,13 @@ struct UpdateArgs {
   int32_t last_mode;              // 1 when n == N-1: evaluate the error
   double tol;                     // convergence tolerance (<= 0: off)
   int32_t check_conv;             // 1: update convergence flags
+  int32_t rmax;                   // largest rank (LDS sizing of the wave kernel)
+  int64_t wave_lds_doubles;       // > 0: wavefront-per-model kernel, LDS per wave
+  int32_t waves_per_block;
 };
 
+// LDS (doubles) one wavefront of the wavefront-per-model update needs.
+int64_t update_wave_lds_doubles(int rmax, int rows);
 hipError_t launch_update(const UpdateArgs& a, hipStream_t s);
 
 struct GramArgs {
@@ -117,8 +123,8 @@ hipError_t launch_reduce(const double* partial, int32_t splits, int32_t rows,
 // Preparation kernels.
 hipError_t launch_copy_tensor(const void* src, int32_t src_f32, void* dst,
                               int64_t count, hipStream_t s);
-hipError_t launch_split_tensor(const void* src, int32_t src_f32, uint16_t* hi,
-                               uint16_t* lo, int64_t count, hipStream_t s);
+hipError_t launch_split_tensor(const void* src, int32_t src_f32, uint16_t* planes,
+                               int32_t nterm, int64_t count, hipStream_t s);
 hipError_t launch_slice_norms(const void* T, int32_t t_f32, int64_t inner,
                               int32_t I, int64_t outer, double* partial,
                               int32_t chunks, double* s_out, hipStream_t s);
@@ -177,11 +183,13 @@ struct jkc_ctx {
   std::vector<int32_t> h_rank, h_left, h_off, h_order, h_colp, h_colmodel;
   std::vector<int64_t> h_goff;
   int64_t gsize = 0;  // doubles per Gram plane
+  int32_t rmax = 0;   // largest model rank
+  int64_t maxI = 0;   // largest mode size
 
   // device buffers (all inside the caller's workspace)
   const void* T = nullptr;       // FP64 path tensor (f64 or f32)
-  uint16_t* T_hi = nullptr;      // split path planes
-  uint16_t* T_lo = nullptr;
+  uint16_t* T_planes = nullptr;  // split paths: nterm bf16 planes of P elements
+  int32_t nterm = 0;
   double* U[jkc::kMaxOrder] = {nullptr, nullptr, nullptr, nullptr};
   double* G[jkc::kMaxOrder] = {nullptr, nullptr, nullptr, nullptr};
   double* Mbuf = nullptr;        // [max I_n][ldc]
@@ -211,6 +219,7 @@ struct jkc_ctx {
   int split_max[jkc::kMaxOrder] = {1, 1, 1, 1};
   std::string describe[jkc::kMaxOrder];
   bool lambda_is_one = true;     // lambda folded into the last factor
+  bool wave_update = true;       // wavefront-per-model update when it fits
 
   // MTTKRP kernel timing (jk_cals_profile)
   bool prof_on = false;

@@ -26,9 +26,10 @@
 //
 // Matrix instruction (INSTR):
 //   0: v_mfma_f64_16x16x4 -- one 16x16 tile per instruction;
-//   1: v_mfma_f64_4x4x4 (4 blocks) with the A operand broadcast from block q
-//      (CBSZ = 2, ABID = q): four instructions cover a 16x16x4 step, block b
-//      of the wave producing rows 4q..4q+3 and columns 4b..4b+3.
+//   1: v_mfma_f64_4x4x4 (4 independent 4x4 blocks per instruction): four
+//      instructions q = 0..3 cover a 16x16x4 step, block b producing rows
+//      4b..4b+3 and columns 4((b+q) mod 4)..+3 (a diagonal schedule, so the
+//      A operand is loaded once and four B operands are rotated).
 // Partials of the K chunks are summed later in a fixed order, so results are
 // bitwise repeatable for a fixed tiling.
 #include "jkc_internal.hpp"
@@ -40,17 +41,12 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int kPad = 8;  // LDS row padding (doubles)
+constexpr int kXcds = 8;  // accelerator complex dies on MI355X
 
-// Lane layouts of v_mfma_f64_4x4x4 (4 blocks of 16 lanes); o = lane % 16.
-//   A (4x4, rows i, depth k):   lane offset o = i + 4k
-//   B (depth k, columns j):     lane offset o = j + 4k
-//   D (rows i, columns j):      lane offset o = j + 4i
-__device__ constexpr int l4_a_row(int o) { return o & 3; }
-__device__ constexpr int l4_a_k(int o) { return o >> 2; }
-__device__ constexpr int l4_b_col(int o) { return o & 3; }
-__device__ constexpr int l4_b_k(int o) { return o >> 2; }
-__device__ constexpr int l4_d_row(int o) { return o >> 2; }
-__device__ constexpr int l4_d_col(int o) { return o & 3; }
+// Lane layout of v_mfma_f64_4x4x4 (4 blocks), measured on gfx950: lane l
+// belongs to block b = (l >> 2) & 3 and holds, with e = l & 3, kq = l >> 4,
+//   A(i = e, k = kq),  B(k = kq, j = e),  D(i = kq, j = e)
+// of that block's 4x4x4 product.
 
 // Incremental walk over columns j of the unfolding: the multi-index of the
 // other modes (lowest mode fastest, Eq. (3)), the tensor offset of the
@@ -110,10 +106,17 @@ k_mttkrp_f64(const MttkrpArgs a) {
   const int wm = wave % WM;
   const int wn = wave / WM;
 
-  const int tile = blockIdx.x;
-  const int split = blockIdx.y;
-  const int mt = tile % a.mtiles;
-  const int nt = tile / a.mtiles;
+  // Block -> (column tile, row tile, K chunk).  Work-groups are dealt to the
+  // 8 XCDs round-robin; remapping so that each XCD receives a contiguous
+  // run of logical blocks (column tile fastest) keeps the blocks that share
+  // one slice of the unfolding on the same XCD, where it stays in L2.
+  const int total = gridDim.x;
+  int logical = blockIdx.x;
+  const int per_xcd = total / kXcds;
+  if (logical < per_xcd * kXcds) logical = (logical % kXcds) * per_xcd + logical / kXcds;
+  const int nt = logical % a.ntiles;
+  const int mt = (logical / a.ntiles) % a.mtiles;
+  const int split = logical / (a.ntiles * a.mtiles);
   const int i0 = mt * BM;
   const int c0 = nt * BN;
   const int64_t kbeg = (int64_t)split * a.kchunk;
@@ -196,6 +199,9 @@ k_mttkrp_f64(const MttkrpArgs a) {
 
   const int o16 = lane & 15;
   const int blk = lane >> 4;
+  const int b4 = (lane >> 2) & 3;   // 4x4x4 block of this lane
+  const int e4 = lane & 3;
+  const int kq4 = lane >> 4;
   for (int s = 0; s < nsteps; ++s) {
     const int buf = s & 1;
     const bool more = s + 1 < nsteps;
@@ -218,21 +224,23 @@ k_mttkrp_f64(const MttkrpArgs a) {
           for (int y = 0; y < TN; ++y)
             acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
       } else {
+        double bq[TN][4];
 #pragma unroll
         for (int x = 0; x < TM; ++x)
-          av[x] = As[buf][kk + l4_a_k(o16)][wm * TM * 16 + x * 16 + 4 * blk + l4_a_row(o16)];
+          av[x] = As[buf][kk + kq4][wm * TM * 16 + x * 16 + 4 * b4 + e4];
 #pragma unroll
         for (int y = 0; y < TN; ++y)
-          bv[y] = Bs[buf][kk + l4_b_k(o16)][wn * TN * 16 + y * 16 + 4 * blk + l4_b_col(o16)];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            bq[y][q] = Bs[buf][kk + kq4][wn * TN * 16 + y * 16 + 4 * ((b4 + q) & 3) + e4];
 #pragma unroll
         for (int x = 0; x < TM; ++x)
 #pragma unroll
-          for (int y = 0; y < TN; ++y) {
-            acc[x][y][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[x], bv[y], acc[x][y][0], 2, 0, 0);
-            acc[x][y][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[x], bv[y], acc[x][y][1], 2, 1, 0);
-            acc[x][y][2] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[x], bv[y], acc[x][y][2], 2, 2, 0);
-            acc[x][y][3] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[x], bv[y], acc[x][y][3], 2, 3, 0);
-          }
+          for (int y = 0; y < TN; ++y)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              acc[x][y][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[x], bq[y][q], acc[x][y][q], 0, 0, 0);
+        (void)bv;
       }
     }
     if (more) store_step(buf ^ 1);
@@ -240,8 +248,8 @@ k_mttkrp_f64(const MttkrpArgs a) {
   }
 
   // Epilogue.  16x16x4: lane l holds, in element r, row 4*r + l/16 and
-  // column l%16 of its tile.  4x4x4 broadcast: element q holds row
-  // 4*q + (D row of o16) and column 4*(l/16) + (D column of o16).
+  // column l%16 of its tile.  4x4x4: element q holds row 4*b + l/16 and
+  // column 4*((b+q) mod 4) + (l mod 4), b = (l/4) mod 4.
   double* __restrict__ out = a.partial + (int64_t)split * a.M * a.ldc;
 #pragma unroll
   for (int x = 0; x < TM; ++x)
@@ -254,8 +262,8 @@ k_mttkrp_f64(const MttkrpArgs a) {
           rr = 4 * r + blk;
           cc = o16;
         } else {
-          rr = 4 * r + l4_d_row(o16);
-          cc = 4 * blk + l4_d_col(o16);
+          rr = 4 * b4 + kq4;
+          cc = 4 * ((b4 + r) & 3) + e4;
         }
         const int row = i0 + wm * TM * 16 + x * 16 + rr;
         const int col = c0 + wn * TN * 16 + y * 16 + cc;
@@ -265,7 +273,7 @@ k_mttkrp_f64(const MttkrpArgs a) {
 
 template <int WM, int WN, int TM, int TN, int BK, int INSTR>
 hipError_t launch_f64(const MttkrpArgs& a, hipStream_t s) {
-  dim3 grid(a.mtiles * a.ntiles, a.splits);
+  dim3 grid(a.mtiles * a.ntiles * a.splits);
   hipLaunchKernelGGL((k_mttkrp_f64<WM, WN, TM, TN, BK, INSTR>), grid, dim3(64 * WM * WN), 0, s, a);
   return hipGetLastError();
 }
@@ -277,14 +285,16 @@ hipError_t launch_f64(const MttkrpArgs& a, hipStream_t s) {
 
 const std::vector<MttkrpVariant>& mttkrp_f64_variants() {
   static const std::vector<MttkrpVariant> v = {
-      JKC_F64_VARIANT(2, 2, 2, 2, 16, 0),   // 64 x 64
-      JKC_F64_VARIANT(2, 2, 2, 4, 16, 0),   // 64 x 128
+      JKC_F64_VARIANT(2, 2, 2, 2, 16, 1),   // 64 x 64, 4x4x4
+      JKC_F64_VARIANT(2, 2, 2, 4, 16, 1),   // 64 x 128
+      JKC_F64_VARIANT(2, 2, 4, 2, 16, 1),   // 128 x 64
+      JKC_F64_VARIANT(1, 4, 7, 2, 16, 1),   // 112 x 128
+      JKC_F64_VARIANT(2, 2, 1, 1, 32, 1),   // 32 x 32
+      JKC_F64_VARIANT(4, 1, 1, 1, 32, 1),   // 64 x 16
+      JKC_F64_VARIANT(4, 1, 2, 1, 32, 1),   // 128 x 16
+      JKC_F64_VARIANT(2, 2, 2, 2, 16, 0),   // 64 x 64, 16x16x4
       JKC_F64_VARIANT(2, 2, 4, 2, 16, 0),   // 128 x 64
       JKC_F64_VARIANT(1, 4, 7, 2, 16, 0),   // 112 x 128
-      JKC_F64_VARIANT(2, 2, 4, 4, 16, 0),   // 128 x 128
-      JKC_F64_VARIANT(2, 2, 1, 1, 32, 0),   // 32 x 32
-      JKC_F64_VARIANT(4, 1, 1, 1, 32, 0),   // 64 x 16
-      JKC_F64_VARIANT(4, 1, 2, 1, 32, 0),   // 128 x 16
   };
   return v;
 }

@@ -59,15 +59,19 @@ __device__ inline double bf16_to_double(uint16_t h) {
   return (double)__uint_as_float((uint32_t)h << 16);
 }
 
-__global__ void k_split_tensor(const void* src, int32_t src_f32, uint16_t* hi, uint16_t* lo,
-                               int64_t n) {
+// x = t_1 + t_2 + ... : t_1 = bf16(x), t_2 = bf16(x - t_1), ... (each
+// remainder exact in float64), plane t at planes + t * n.
+__global__ void k_split_tensor(const void* src, int32_t src_f32, uint16_t* planes,
+                               int32_t nterm, int64_t n) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const double x = src_f32 ? (double)static_cast<const float*>(src)[e]
-                             : static_cast<const double*>(src)[e];
-    const uint16_t h = bf16_rne(x);
-    hi[e] = h;
-    lo[e] = bf16_rne(x - bf16_to_double(h));
+    double x = src_f32 ? (double)static_cast<const float*>(src)[e]
+                       : static_cast<const double*>(src)[e];
+    for (int t = 0; t < nterm; ++t) {
+      const uint16_t h = bf16_rne(x);
+      planes[(int64_t)t * n + e] = h;
+      x -= bf16_to_double(h);
+    }
   }
 }
 
@@ -194,10 +198,10 @@ hipError_t launch_copy_tensor(const void* src, int32_t src_f32, void* dst, int64
   return hipGetLastError();
 }
 
-hipError_t launch_split_tensor(const void* src, int32_t src_f32, uint16_t* hi, uint16_t* lo,
-                               int64_t count, hipStream_t s) {
-  hipLaunchKernelGGL(k_split_tensor, dim3(grid_for(count)), dim3(256), 0, s, src, src_f32, hi,
-                     lo, count);
+hipError_t launch_split_tensor(const void* src, int32_t src_f32, uint16_t* planes,
+                               int32_t nterm, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_split_tensor, dim3(grid_for(count)), dim3(256), 0, s, src, src_f32,
+                     planes, nterm, count);
   return hipGetLastError();
 }
 

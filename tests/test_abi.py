@@ -62,7 +62,7 @@ def test_workspace_size_valid_problem():
     (dict(left_out=[-2, 3]), "left_out"),
     (dict(left_out=[-1, 4]), "left_out"),
     (dict(dims=[1, 5, 6], left_out=[-1, 0]), "only sample"),
-    (dict(precision=2), "precision"),
+    (dict(precision=3), "precision"),
     (dict(tensor_dtype=5), "tensor_dtype"),
     (dict(precision=1, copy_tensor=0), "copy_tensor"),
     (dict(copy_tensor=3), "copy_tensor"),

@@ -31,7 +31,7 @@ def test_loss_and_gradient_match_oracle(seed, dims, ranks, lo):
     wl = synth.random_problem(seed, dims, ranks, lo, noise=0.2)
     say("grad parity", seed)
     ctx = make_ctx(wl)
-    facs = [torch.from_numpy(u).cuda() for u in wl.init]
+    facs = [torch.from_numpy(u).cuda().requires_grad_() for u in wl.init]
     loss = jk.JKCPLoss.apply(ctx, *facs)
     w = torch.linspace(0.5, 2.0, wl.K, dtype=torch.float64, device="cuda")
     grads = torch.autograd.grad((loss * w).sum(), facs)
@@ -58,8 +58,7 @@ def test_gradient_matches_central_differences():
     ctx = make_ctx(wl)
     base = [torch.from_numpy(u).cuda() for u in wl.init]
     base[0][4, 2:5] = 0.0  # the left-out row of model 1 is not a parameter
-    loss = torch.empty(wl.K, dtype=torch.float64, device="cuda")
-    facs = [b.clone() for b in base]
+    facs = [b.clone().requires_grad_() for b in base]
     Lt = jk.JKCPLoss.apply(ctx, *facs)
     grads = [to_np(x) for x in torch.autograd.grad(Lt.sum(), facs)]
     h = 1e-3

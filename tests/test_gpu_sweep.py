@@ -158,3 +158,20 @@ def test_remove_slice_bit_exact():
                 out = to_np(jk.jk_cals_remove_slice(Td, dims, nh, p))
                 ref = np.delete(T, p, axis=nh).ravel(order="F")
                 assert out.dtype == ref.dtype and np.array_equal(out, ref)
+
+
+def test_wave_and_block_update_kernels_agree():
+    """The wavefront-per-model and block-per-model update kernels compute the
+    same update (same summation orders for U, lambda, Gram)."""
+    wl = synth.random_problem(29, (35, 28, 22), [5, 3, 7, 1], [-1, 0, 34, 9], noise=0.05)
+    a = make_ctx(wl)
+    b = make_ctx(wl)
+    b.set_update_kernel(1)
+    a.sweep(4)
+    b.sweep(4)
+    for n in range(3):
+        ua, la = (to_np(x) for x in a.get_factors(n))
+        ub, lb = (to_np(x) for x in b.get_factors(n))
+        assert rel(ua, ub) <= 1e-14 and rel(la, lb) <= 1e-14
+    ea, eb = to_np(a.get_status()[0]), to_np(b.get_status()[0])
+    assert np.allclose(ea, eb, rtol=1e-12, atol=0)
