@@ -63,7 +63,7 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "c2":
         wl = synth.config2()
-        desc_w = ("c2: 100x200x200 f64 fluorescence-like tensor, rank 5, 2% noise; "
+        desc_w = ("c2: 100x200x200 f64 fluorescence-like tensor, rank 5, 2%% noise; "
                   "100 leave-one-out submodels of rank 5; %d ALS sweeps")
         prec_name = args.precision or "fp64"
     elif args.workload == "c3":
@@ -73,7 +73,7 @@ def main():
         prec_name = args.precision or "fp64"
     else:
         wl = synth.config4()
-        desc_w = ("c4: 200x120x100x80 f64 rank-12 tensor, 1% noise; 200 leave-one-out submodels "
+        desc_w = ("c4: 200x120x100x80 f64 rank-12 tensor, 1%% noise; 200 leave-one-out submodels "
                   "of rank 12; split-precision MTTKRP; %d ALS sweeps")
         prec_name = args.precision or "bf16x3"
     precision = {"fp64": jk.JKC_FP64, "bf16x3": jk.JKC_SPLIT_BF16X3,

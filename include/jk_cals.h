@@ -187,11 +187,16 @@ jkc_status jk_cals_tune(jkc_ctx *ctx, int32_t reps);
 /* The current tiling of `mode` as text, e.g. "f64 wm2 wn2 tm2 tn2 bk16 s8". */
 const char *jk_cals_describe(jkc_ctx *ctx, int32_t mode);
 
-/* Choose the per-model update kernel: 0 = one wavefront per model with the
- * model's rows in LDS whenever they fit (default), 1 = one 256-thread block
- * per model.  Both compute the same update with the same summation order
- * for U, lambda and the Gram matrices.  Host only. */
+/* Choose the per-model update kernel: 0 = the model's rows staged in LDS,
+ * with the split-K MTTKRP reduction fused in, whenever they fit (default);
+ * 1 = a separate reduction kernel, then the update working in global
+ * memory.  Both compute the same sums in the same order.  Host only. */
 jkc_status jk_cals_set_update_kernel(jkc_ctx *ctx, int32_t which);
+
+/* Replay multi-sweep runs of jk_cals_sweep from a HIP graph of one sweep,
+ * captured on first use (enable = 1, default), or launch every kernel
+ * directly (enable = 0).  The results are identical.  Host only. */
+jkc_status jk_cals_set_sweep_graph(jkc_ctx *ctx, int32_t enable);
 
 /* Number of MTTKRP tilings compiled for the context's precision (0 if ctx is
  * NULL). */

@@ -90,6 +90,7 @@ def lib() -> ctypes.CDLL:
         "jk_cals_describe": (ctypes.c_char_p, [VP, I32]),
         "jk_cals_num_tilings": (I32, [VP]),
         "jk_cals_set_update_kernel": (I32, [VP, I32]),
+        "jk_cals_set_sweep_graph": (I32, [VP, I32]),
         "jk_cals_profile": (I32, [VP, I32]),
         "jk_cals_profile_read": (I32, [VP, VP, VP]),
         "jk_cals_set_tiling": (I32, [VP, I32, I32, I32]),
@@ -304,6 +305,9 @@ class JkCals:
     def set_update_kernel(self, which: int):
         _check(lib().jk_cals_set_update_kernel(self.ctx, int(which)))
 
+    def set_sweep_graph(self, enable: bool):
+        _check(lib().jk_cals_set_sweep_graph(self.ctx, 1 if enable else 0))
+
     def num_tilings(self) -> int:
         return int(lib().jk_cals_num_tilings(self.ctx))
 
@@ -370,6 +374,10 @@ def jk_cals_profile_read(ctx: JkCals):
 
 def jk_cals_set_update_kernel(ctx: JkCals, which: int):
     return ctx.set_update_kernel(which)
+
+
+def jk_cals_set_sweep_graph(ctx: JkCals, enable: bool):
+    return ctx.set_sweep_graph(enable)
 
 
 def jk_cals_num_tilings(ctx: JkCals) -> int:

@@ -221,7 +221,7 @@ double model_cost(const Tiling& t, const ModeShape& s) {
   const int64_t nt = (s.ncols + t.bn() - 1) / t.bn();
   const double useful = (double)s.M * s.ncols;
   const double padded = (double)mt * t.bm() * nt * t.bn();
-  const double per_step = (double)t.tm * t.tn * (t.bk / 4) * (t.instr == 1 ? 1.0 : 1.45);
+  const double per_step = (double)t.tm * t.tn * (t.bk / 4) * (t.instr == 0 ? 1.45 : t.instr == 2 ? 0.25 : 1.0);
   const double hide = per_step / (per_step + 6.0);
   const double blocks = (double)mt * nt * t.splits;
   const double fill = std::min(1.0, blocks / (2.0 * kNumCU)) * std::min(1.0, (double)(t.wm * t.wn) / 4.0);
@@ -260,7 +260,10 @@ std::string describe_tiling(const Tiling& t, int precision) {
   snprintf(buf, sizeof(buf), "%s v%d wm%d wn%d tm%d tn%d bk%d s%d %s",
            precision == JKC_SPLIT_BF16X3 ? "bf16x3" : precision == JKC_SPLIT_BF16X6 ? "bf16x6" : "f64",
            t.variant, t.wm, t.wn, t.tm, t.tn, t.bk, t.splits,
-           t.instr == 1 ? "mfma4x4x4" : t.instr == 0 ? "mfma16x16x4" : "mfma16x16x32bf16");
+           precision != JKC_FP64 ? "mfma16x16x32bf16"
+           : t.instr == 2        ? "mfma4x4x4-strips"
+           : t.instr == 1        ? "mfma4x4x4-diagonal"
+                                 : "mfma16x16x4");
   return buf;
 }
 
@@ -440,16 +443,36 @@ jkc_status enqueue_mttkrp_reduced(jkc_ctx* ctx, int n, double* out, int ldo, int
 }
 
 jkc_status enqueue_update(jkc_ctx* ctx, int n, double tol, int check_conv) {
-  JKC_TRY(enqueue_mttkrp_reduced(ctx, n, ctx->Mbuf, ctx->ldc, ctx->ldc));
+  constexpr int64_t kLdsBudget = 64 * 1024;
+  constexpr int kFuseMaxSplits = 2;
+  const int64_t lds = update_lds_doubles(ctx->rmax, (int)ctx->dims[n]);
+  const bool staged = ctx->lds_update && lds * 8 <= kLdsBudget;
+  const int splits = effective_splits(ctx, n, ctx->tiling[n]);
   UpdateArgs a{};
+  if (staged && splits <= kFuseMaxSplits) {
+    // few partials: the update sums them itself while staging M in LDS
+    JKC_TRY(enqueue_mttkrp(ctx, n, ctx->tiling[n]));
+    a.partial = splits > 1 ? ctx->partial : ctx->Mbuf;
+    a.splits = splits;
+    a.lds_doubles = lds;
+  } else if (staged) {
+    // many partials: a full-chip reduction first, then the staged update
+    JKC_TRY(enqueue_mttkrp_reduced(ctx, n, ctx->Mbuf, ctx->ldc, ctx->ldc));
+    a.partial = ctx->Mbuf;
+    a.splits = 1;
+    a.lds_doubles = lds;
+  } else {
+    JKC_TRY(enqueue_mttkrp_reduced(ctx, n, ctx->Mbuf, ctx->ldc, ctx->ldc));
+    a.partial = nullptr;
+    a.splits = 1;
+    a.lds_doubles = 0;
+  }
   a.mt = ctx->table();
   a.N = ctx->N;
   a.n = n;
   a.nhat = ctx->nhat;
   a.In = (int32_t)ctx->dims[n];
   a.ldc = ctx->ldc;
-  a.partial = nullptr;
-  a.splits = 1;
   a.Mout = ctx->Mbuf;
   a.U = ctx->U[n];
   for (int m = 0; m < kMaxOrder; ++m) a.G[m] = ctx->G[m];
@@ -464,19 +487,54 @@ jkc_status enqueue_update(jkc_ctx* ctx, int n, double tol, int check_conv) {
   a.tol = tol;
   a.check_conv = check_conv;
   a.rmax = ctx->rmax;
-  // wavefront-per-model kernel when a model's rows fit in 64 KB of LDS with
-  // at least one wavefront per block
-  const int64_t per_wave = update_wave_lds_doubles(ctx->rmax, (int)ctx->dims[n]) * 8;
-  const int64_t budget = 64 * 1024;
-  a.waves_per_block = (int32_t)std::min<int64_t>(4, budget / per_wave);
-  a.wave_lds_doubles = a.waves_per_block > 0 && ctx->wave_update ? per_wave / 8 : 0;
   JKC_HIP(launch_update(a, ctx->stream));
   return JKC_OK;
 }
 
+void drop_graph(jkc_ctx* ctx) {
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  ctx->graph_exec = nullptr;
+}
+
+// One sweep (all modes: MTTKRP, reduction, update) captured once into a HIP
+// graph on a private stream, then replayed on the context's stream: the
+// sweep is a fixed chain of kernels whose arguments never change for the
+// life of the context (buffers live in the workspace; tilings only change
+// through calls that drop the graph).  The graph holds kernel nodes only.
+jkc_status build_sweep_graph(jkc_ctx* ctx) {
+  if (ctx->graph_exec) return JKC_OK;
+  hipStream_t cap = nullptr;
+  JKC_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipStream_t user = ctx->stream;
+  ctx->stream = cap;
+  jkc_status st = JKC_OK;
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    st = fail(JKC_EDEVICE, "hipStreamBeginCapture failed");
+  } else {
+    for (int n = 0; n < ctx->N && st == JKC_OK; ++n) st = enqueue_update(ctx, n, 0.0, 0);
+    const hipError_t e = hipStreamEndCapture(cap, &graph);
+    if (st == JKC_OK && e != hipSuccess) st = fail(JKC_EDEVICE, "hipStreamEndCapture failed");
+  }
+  ctx->stream = user;
+  if (st == JKC_OK && hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    ctx->graph_exec = nullptr;
+    st = fail(JKC_EDEVICE, "hipGraphInstantiate failed");
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cap);
+  return st;
+}
+
 jkc_status enqueue_sweeps(jkc_ctx* ctx, int nsweeps, double tol, int check_conv) {
-  for (int s = 0; s < nsweeps; ++s)
-    for (int n = 0; n < ctx->N; ++n) JKC_TRY(enqueue_update(ctx, n, tol, check_conv));
+  const bool graph = ctx->use_graph && !ctx->prof_on && !check_conv && nsweeps > 1;
+  if (graph) {
+    JKC_TRY(build_sweep_graph(ctx));
+    for (int s = 0; s < nsweeps; ++s) JKC_HIP(hipGraphLaunch(ctx->graph_exec, ctx->stream));
+  } else {
+    for (int s = 0; s < nsweeps; ++s)
+      for (int n = 0; n < ctx->N; ++n) JKC_TRY(enqueue_update(ctx, n, tol, check_conv));
+  }
   if (nsweeps > 0) ctx->lambda_is_one = false;
   return JKC_OK;
 }
@@ -889,6 +947,7 @@ jkc_status jk_cals_tune(jkc_ctx* ctx, int32_t reps) {
     }
     ctx->tiling[n] = best;
     ctx->describe[n] = describe_tiling(best, ctx->precision);
+    drop_graph(ctx);
     if (result == JKC_OK) tune_store(ctx, n, best);
   }
   (void)hipEventDestroy(e0);
@@ -905,7 +964,16 @@ const char* jk_cals_describe(jkc_ctx* ctx, int32_t mode) {
 jkc_status jk_cals_set_update_kernel(jkc_ctx* ctx, int32_t which) {
   JKC_TRY(check_ctx(ctx));
   if (which != 0 && which != 1) return fail(JKC_EINVAL, "which must be 0 or 1");
-  ctx->wave_update = which == 0;
+  ctx->lds_update = which == 0;
+  drop_graph(ctx);
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_set_sweep_graph(jkc_ctx* ctx, int32_t enable) {
+  JKC_TRY(check_ctx(ctx));
+  ctx->use_graph = enable != 0;
+  drop_graph(ctx);
   g_last_error.clear();
   return JKC_OK;
 }
@@ -924,6 +992,7 @@ jkc_status jk_cals_set_tiling(jkc_ctx* ctx, int32_t mode, int32_t variant, int32
   const ModeShape shape = mode_shape(ctx, mode, ctx->split_max[mode]);
   ctx->tiling[mode] = make_tiling(vars, variant, shape, splits);
   ctx->describe[mode] = describe_tiling(ctx->tiling[mode], ctx->precision);
+  drop_graph(ctx);
   g_last_error.clear();
   return JKC_OK;
 }

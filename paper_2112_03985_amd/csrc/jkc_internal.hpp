@@ -23,7 +23,8 @@ constexpr double kPivotTolPerRank = 64.0 * 2.220446049250313e-16;
 
 // ---------------------------------------------------------------------------
 // MTTKRP tiling.  A block has WM x WN wavefronts; each wavefront owns a
-// (TM*16) x (TN*16) tile of the output made of 16x16 MFMA tiles; the block
+// (TM*16) x (TN*16) tile of the output made of 16x16 MFMA tiles ((TM*4) x
+// (TN*16) of 4x16 strips for the row-strip float64 instruction); the block
 // walks the K dimension (columns of the unfolding) in steps of BK.  The K
 // range is cut into S contiguous chunks, one per grid row, whose partial
 // products are summed afterwards in a fixed order.
@@ -32,7 +33,7 @@ struct Tiling {
   int variant = -1;   // index into the kernel table (precision specific)
   int wm = 0, wn = 0, tm = 0, tn = 0, bk = 0, instr = 0;
   int splits = 1;
-  int bm() const { return wm * tm * 16; }
+  int bm() const { return wm * tm * (instr == 2 ? 4 : 16); }
   int bn() const { return wn * tn * 16; }
 };
 
@@ -82,9 +83,9 @@ struct UpdateArgs {
   int32_t N, n, nhat;
   int32_t In;                     // rows of the updated mode
   int32_t ldc;
-  const double* partial;          // [splits][In][ldc] MTTKRP partials
+  const double* partial;          // [splits][In][ldc] MTTKRP partials (LDS kernel)
   int32_t splits;
-  double* Mout;                   // [In][ldc] reduced MTTKRP (row-p zeroed)
+  double* Mout;                   // [In][ldc] reduced MTTKRP (global kernel)
   double* U;                      // [In][ldc] factor of mode n (output)
   double* G[kMaxOrder];           // Gram planes, one per mode
   double* lambda;                 // [ldc]
@@ -97,13 +98,12 @@ struct UpdateArgs {
   int32_t last_mode;              // 1 when n == N-1: evaluate the error
   double tol;                     // convergence tolerance (<= 0: off)
   int32_t check_conv;             // 1: update convergence flags
-  int32_t rmax;                   // largest rank (LDS sizing of the wave kernel)
-  int64_t wave_lds_doubles;       // > 0: wavefront-per-model kernel, LDS per wave
-  int32_t waves_per_block;
+  int32_t rmax;                   // largest rank (LDS sizing)
+  int64_t lds_doubles;            // > 0: LDS-staged kernel with this much dynamic LDS
 };
 
-// LDS (doubles) one wavefront of the wavefront-per-model update needs.
-int64_t update_wave_lds_doubles(int rmax, int rows);
+// Dynamic LDS (doubles) of the LDS-staged update for a mode with `rows` rows.
+int64_t update_lds_doubles(int rmax, int rows);
 hipError_t launch_update(const UpdateArgs& a, hipStream_t s);
 
 struct GramArgs {
@@ -219,7 +219,9 @@ struct jkc_ctx {
   int split_max[jkc::kMaxOrder] = {1, 1, 1, 1};
   std::string describe[jkc::kMaxOrder];
   bool lambda_is_one = true;     // lambda folded into the last factor
-  bool wave_update = true;       // wavefront-per-model update when it fits
+  bool lds_update = true;        // LDS-staged fused update when it fits
+  bool use_graph = true;         // replay sweeps from a captured HIP graph
+  hipGraphExec_t graph_exec = nullptr;
 
   // MTTKRP kernel timing (jk_cals_profile)
   bool prof_on = false;
@@ -228,6 +230,7 @@ struct jkc_ctx {
   size_t prof_used = 0;
   ~jkc_ctx() {
     for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
   }
 
   jkc::ModelTable table() const {

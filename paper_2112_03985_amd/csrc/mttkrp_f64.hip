@@ -29,9 +29,15 @@
 //   1: v_mfma_f64_4x4x4 (4 independent 4x4 blocks per instruction): four
 //      instructions q = 0..3 cover a 16x16x4 step, block b producing rows
 //      4b..4b+3 and columns 4((b+q) mod 4)..+3 (a diagonal schedule, so the
-//      A operand is loaded once and four B operands are rotated).
+//      A operand is loaded once and four B operands are rotated);
+//   2: v_mfma_f64_4x4x4 in row strips: all four blocks take the same 4 rows
+//      of A and block b columns 4b..4b+3 of a 16-column group, so one
+//      instruction is a 4 x 16 x 4 step and tiles need only multiples of 4
+//      rows (no padding of 100- or 200-row modes to 16).
 // Partials of the K chunks are summed later in a fixed order, so results are
 // bitwise repeatable for a fixed tiling.
+#include <type_traits>
+
 #include "jkc_internal.hpp"
 
 namespace jkc {
@@ -86,16 +92,19 @@ template <int WM, int WN, int TM, int TN, int BK, int INSTR>
 __global__ void __launch_bounds__(64 * WM * WN)
 k_mttkrp_f64(const MttkrpArgs a) {
   constexpr int NT = 64 * WM * WN;
-  constexpr int BM = WM * TM * 16;
+  constexpr int RPT = INSTR == 2 ? 4 : 16;   // rows per matrix-core tile
+  constexpr int BM = WM * TM * RPT;
+  constexpr int BMP = (BM + 15) / 16 * 16;    // rows staged in LDS
   constexpr int BN = WN * TN * 16;
-  constexpr int LDA = BM + kPad;
+  constexpr int LDA = BMP + kPad;
   constexpr int LDB = BN + kPad;
-  constexpr int VA = BM * BK / NT;   // A elements per thread per step (one column)
+  constexpr int VA = BMP * BK / NT;  // A elements per thread per step (one column)
   constexpr int VB = BN * BK / NT;   // B elements per thread per step (one column)
   static_assert(BK % 4 == 0, "BK");
-  static_assert(VA >= 1 && VA * NT == BM * BK, "A tile must split evenly over threads");
+  static_assert(VA >= 1 && VA * NT == BMP * BK, "A tile must split evenly over threads");
   static_assert(VB >= 1 && VB * NT == BN * BK, "B tile must split evenly over threads");
-  static_assert(BM % VA == 0 && BN % VB == 0, "vector width");
+  static_assert(BMP % VA == 0 && BN % VB == 0, "vector width");
+  using AccT = typename std::conditional<INSTR == 2, double, v4d>::type;
 
   __shared__ __attribute__((aligned(16))) double As[2][BK][LDA];
   __shared__ __attribute__((aligned(16))) double Bs[2][BK][LDB];
@@ -126,8 +135,8 @@ k_mttkrp_f64(const MttkrpArgs a) {
   // Thread roles.  A: mode with unit stride (rows contiguous in memory) ->
   // threads run along the rows of one column; otherwise along the columns.
   const bool m_fast = a.stride_n == 1;
-  const int kA = m_fast ? tid / (BM / VA) : tid % BK;
-  const int iA = m_fast ? (tid % (BM / VA)) * VA : (tid / BK) * VA;
+  const int kA = m_fast ? tid / (BMP / VA) : tid % BK;
+  const int iA = m_fast ? (tid % (BMP / VA)) * VA : (tid / BK) * VA;
   const int kB = tid % BK;
   const int cB = (tid / BK) * VB;
 
@@ -148,7 +157,7 @@ k_mttkrp_f64(const MttkrpArgs a) {
     for (int v = 0; v < VA; ++v) {
       const int row = i0 + iA + v;
       double x = 0.0;
-      if (va && row < a.M) {
+      if (va && iA + v < BM && row < a.M) {
         const int64_t addr = toffA + (int64_t)row * a.stride_n;
         x = a.t_is_f32 ? (double)Tf32[addr] : Tf64[addr];
       }
@@ -185,11 +194,11 @@ k_mttkrp_f64(const MttkrpArgs a) {
     }
   };
 
-  v4d acc[TM][TN];
+  AccT acc[TM][TN];
 #pragma unroll
   for (int x = 0; x < TM; ++x)
 #pragma unroll
-    for (int y = 0; y < TN; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int y = 0; y < TN; ++y) acc[x][y] = AccT{};
 
   if (nsteps > 0) {
     load_step();
@@ -213,7 +222,19 @@ k_mttkrp_f64(const MttkrpArgs a) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       double av[TM], bv[TN];
-      if (INSTR == 0) {
+      if constexpr (INSTR == 2) {
+        // row strips: every block gets the same 4 rows of A (same LDS
+        // addresses), block b the columns 4b..4b+3 of each 16-column group
+#pragma unroll
+        for (int x = 0; x < TM; ++x) av[x] = As[buf][kk + kq4][wm * TM * 4 + x * 4 + e4];
+#pragma unroll
+        for (int y = 0; y < TN; ++y) bv[y] = Bs[buf][kk + kq4][wn * TN * 16 + y * 16 + 4 * b4 + e4];
+#pragma unroll
+        for (int x = 0; x < TM; ++x)
+#pragma unroll
+          for (int y = 0; y < TN; ++y)
+            acc[x][y] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
+      } else if constexpr (INSTR == 0) {
 #pragma unroll
         for (int x = 0; x < TM; ++x) av[x] = As[buf][kk + blk][wm * TM * 16 + x * 16 + o16];
 #pragma unroll
@@ -251,6 +272,18 @@ k_mttkrp_f64(const MttkrpArgs a) {
   // column l%16 of its tile.  4x4x4: element q holds row 4*b + l/16 and
   // column 4*((b+q) mod 4) + (l mod 4), b = (l/4) mod 4.
   double* __restrict__ out = a.partial + (int64_t)split * a.M * a.ldc;
+  if constexpr (INSTR == 2) {
+    // row strip x, group y: lane holds row 4x + l/16, column 16y + 4b + l%4
+#pragma unroll
+    for (int x = 0; x < TM; ++x)
+#pragma unroll
+      for (int y = 0; y < TN; ++y) {
+        const int row = i0 + wm * TM * 4 + x * 4 + kq4;
+        const int col = c0 + wn * TN * 16 + y * 16 + 4 * b4 + e4;
+        if (row < a.M && col < a.ldc) out[(int64_t)row * a.ldc + col] = acc[x][y];
+      }
+    return;
+  } else {
 #pragma unroll
   for (int x = 0; x < TM; ++x)
 #pragma unroll
@@ -269,6 +302,7 @@ k_mttkrp_f64(const MttkrpArgs a) {
         const int col = c0 + wn * TN * 16 + y * 16 + cc;
         if (row < a.M && col < a.ldc) out[(int64_t)row * a.ldc + col] = acc[x][y][r];
       }
+  }
 }
 
 template <int WM, int WN, int TM, int TN, int BK, int INSTR>
@@ -285,7 +319,17 @@ hipError_t launch_f64(const MttkrpArgs& a, hipStream_t s) {
 
 const std::vector<MttkrpVariant>& mttkrp_f64_variants() {
   static const std::vector<MttkrpVariant> v = {
-      JKC_F64_VARIANT(2, 2, 2, 2, 16, 1),   // 64 x 64, 4x4x4
+      JKC_F64_VARIANT(1, 4, 25, 2, 16, 2),  // 100 x 128, 4x4x4 row strips
+      JKC_F64_VARIANT(2, 2, 25, 2, 16, 2),  // 200 x 64
+      JKC_F64_VARIANT(2, 2, 25, 1, 16, 2),  // 200 x 32
+      JKC_F64_VARIANT(1, 4, 25, 1, 16, 2),  // 100 x 64
+      JKC_F64_VARIANT(2, 2, 13, 2, 16, 2),  // 104 x 64
+      JKC_F64_VARIANT(2, 2, 13, 4, 16, 2),  // 104 x 128
+      JKC_F64_VARIANT(1, 4, 13, 4, 16, 2),  // 52 x 256
+      JKC_F64_VARIANT(2, 2, 25, 4, 16, 2),  // 200 x 128
+      JKC_F64_VARIANT(1, 4, 16, 2, 16, 2),  // 64 x 128
+      JKC_F64_VARIANT(2, 2, 32, 1, 16, 2),  // 256 x 32
+      JKC_F64_VARIANT(2, 2, 2, 2, 16, 1),   // 64 x 64, 4x4x4 diagonal
       JKC_F64_VARIANT(2, 2, 2, 4, 16, 1),   // 64 x 128
       JKC_F64_VARIANT(2, 2, 4, 2, 16, 1),   // 128 x 64
       JKC_F64_VARIANT(1, 4, 7, 2, 16, 1),   // 112 x 128

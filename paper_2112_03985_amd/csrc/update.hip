@@ -336,117 +336,119 @@ __global__ void __launch_bounds__(kThreads) k_update(const UpdateArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Wavefront-per-model update.  Same mathematics and the same summation
-// orders as k_update, but each 64-lane wavefront owns one model at a time
-// and keeps the model's R x R matrices and its rows of U in LDS, so the
-// whole update needs only wavefront-level synchronisation and one pass
-// over global memory.  Used when a model's rows fit (the host decides).
+// LDS-staged update with the split-K reduction fused in.  Same mathematics
+// and the same summation orders as k_update (so the same bits for U, lambda
+// and the Gram matrices), but the model's block of M is summed over the
+// split-K partials (ascending split order, the order of the stand-alone
+// reduction) straight into LDS, and U is formed, normalised and reduced in
+// LDS, so global memory is touched once for reading and once for writing.
+// Used when the model's rows fit in the dynamic LDS budget.
 // ---------------------------------------------------------------------------
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-__global__ void __launch_bounds__(kThreads) k_update_wave(const UpdateArgs a) {
+__global__ void __launch_bounds__(kThreads) k_update_lds(const UpdateArgs a) {
   extern __shared__ double smem[];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;
-  const int Rp = a.rmax;              // LDS matrices are Rp x (Rp + 1)
+  const int Rp = a.rmax;
   const int ld = Rp + 1;
-  double* base = smem + (size_t)wave * a.wave_lds_doubles;
-  double* H = base;
-  double* L = H + Rp * ld;
-  double* X = L + Rp * ld;            // Linv, or W of the Jacobi fallback
-  double* V = X + Rp * ld;            // Jacobi eigenvectors
-  double* Gs = V + Rp * ld;           // new Gram block
-  double* Hinv = L;                   // overwrites L once Linv is formed
+  double* H = smem;
+  double* L = H + Rp * ld;             // Cholesky factor, then H^{-1}
+  double* X = L + Rp * ld;             // L^{-1}, or Jacobi W
+  double* V = X + Rp * ld;             // Jacobi eigenvectors
+  double* Gs = V + Rp * ld;            // new Gram block
   double* lam = Gs + Rp * ld;
-  double* misc = lam + Rp;            // [0] flag, [1] c, [2] s, [3] cutoff, [4] done
-  double* rows = misc + 8;            // In x ld
-  const double* Gp[kMaxOrder] = {a.G[0], a.G[1], a.G[2], a.G[3]};
+  double* misc = lam + Rp;             // [0] c, [1] s, [2] done, [3] cutoff
+  double* red = misc + 8;              // per-thread partial of the error's inner product
+  double* Ms = red + kThreads;         // In x ld: reduced M block
+  double* Us = Ms + (size_t)a.In * ld; // In x ld: U block
+  __shared__ int s_flag;
+  const int t = threadIdx.x;
+  const int64_t plane = (int64_t)a.In * a.ldc;
 
-  for (int idx = blockIdx.x * nw + wave; idx < a.mt.K; idx += gridDim.x * nw) {
+  for (int idx = blockIdx.x; idx < a.mt.K; idx += gridDim.x) {
     const int k = a.mt.order[idx];
     const int32_t st = a.status[k];
-    if (st & (JKC_ST_CONVERGED | JKC_ST_NONFINITE)) continue;   // frozen (wave-uniform)
+    if (st & (JKC_ST_CONVERGED | JKC_ST_NONFINITE)) continue;  // frozen (block-uniform)
     const int R = a.mt.rank[k];
     const int off = a.mt.off[k];
     const int p = a.mt.left[k];
     const int64_t goff = a.mt.goff[k];
     const int zero_row = (a.n == a.nhat) ? p : -1;
 
-    // H = product of the other modes' Gram blocks, ascending mode order
-    for (int e = lane; e < R * R; e += 64) {
+    // H and the reduced block of M, loads issued together
+    for (int e = t; e < R * R; e += blockDim.x) {
       const int r = e / R, c = e % R;
       double h = 0.0;
       bool first = true;
 #pragma unroll
       for (int m = 0; m < kMaxOrder; ++m) {
         if (m >= a.N || m == a.n) continue;
-        const double g = Gp[m][goff + e];
+        const double* Gm = m == 0 ? a.G[0] : m == 1 ? a.G[1] : m == 2 ? a.G[2] : a.G[3];
+        const double g = Gm[goff + e];
         h = first ? g : h * g;
         first = false;
       }
       H[r * ld + c] = h;
     }
-    if (lane == 0) misc[0] = 1.0;
-    wave_sync();
+    for (int e = t; e < a.In * R; e += blockDim.x) {
+      const int i = e / R, r = e % R;
+      const double* src = a.partial + (int64_t)i * a.ldc + off + r;
+      double m = 0.0;
+      for (int sp = 0; sp < a.splits; ++sp) m += src[sp * plane];
+      Ms[i * ld + r] = (i == zero_row) ? 0.0 : m;
+    }
+    __syncthreads();
 
-    // Cholesky, column by column
+    // Cholesky, pivots by thread 0, the column below by threads i > j
     double maxdiag = 0.0;
     for (int j = 0; j < R; ++j) maxdiag = fmax(maxdiag, H[j * ld + j]);
     const double thresh = kPivotTolPerRank * R * maxdiag;
+    if (t == 0) s_flag = 1;
     for (int j = 0; j < R; ++j) {
-      if (lane == 0) {
+      if (t == 0) {
         double d = H[j * ld + j];
         for (int q = 0; q < j; ++q) d -= L[j * ld + q] * L[j * ld + q];
         const bool ok = isfinite(d) && d > thresh && maxdiag > 0.0 && isfinite(maxdiag);
-        if (!ok) misc[0] = 0.0;
+        if (!ok) s_flag = 0;
         L[j * ld + j] = ok ? sqrt(d) : 1.0;
       }
-      wave_sync();
-      if (lane > j && lane < R) {
-        double v = H[lane * ld + j];
-        for (int q = 0; q < j; ++q) v -= L[lane * ld + q] * L[j * ld + q];
-        L[lane * ld + j] = v / L[j * ld + j];
+      __syncthreads();
+      if (t > j && t < R) {
+        double v = H[t * ld + j];
+        for (int q = 0; q < j; ++q) v -= L[t * ld + q] * L[j * ld + q];
+        L[t * ld + j] = v / L[j * ld + j];
       }
-      wave_sync();
+      __syncthreads();
     }
-    const bool chol_ok = misc[0] != 0.0;
+    const bool chol_ok = s_flag != 0;
+    __syncthreads();
 
     if (chol_ok) {
-      // Linv = L^{-1}, one column per lane; then Hinv = Linv^T Linv (into L)
-      if (lane < R) {
-        const int j = lane;
+      if (t < R) {
+        const int j = t;
         for (int r = 0; r < R; ++r) {
           double v = (r == j) ? 1.0 : 0.0;
           for (int q = j; q < r; ++q) v -= L[r * ld + q] * X[q * ld + j];
           X[r * ld + j] = (r < j) ? 0.0 : v / L[r * ld + r];
         }
       }
-      wave_sync();
-      for (int e = lane; e < R * R; e += 64) {
+      __syncthreads();
+      for (int e = t; e < R * R; e += blockDim.x) {
         const int r = e / R, c = e % R;
         if (r <= c) {
           double acc = 0.0;
           for (int q = c; q < R; ++q) acc += X[q * ld + r] * X[q * ld + c];
-          Hinv[r * ld + c] = acc;
-          Hinv[c * ld + r] = acc;
+          L[r * ld + c] = acc;
+          L[c * ld + r] = acc;
         }
       }
-      wave_sync();
+      __syncthreads();
     } else {
-      // eigen pseudoinverse by cyclic Jacobi (rare fallback)
-      for (int e = lane; e < R * R; e += 64) {
+      for (int e = t; e < R * R; e += blockDim.x) {
         const int r = e / R, c = e % R;
         X[r * ld + c] = H[r * ld + c];
         V[r * ld + c] = (r == c) ? 1.0 : 0.0;
       }
-      wave_sync();
+      __syncthreads();
       for (int sweep = 0; sweep < 40; ++sweep) {
-        if (lane == 0) {
+        if (t == 0) {
           double offd = 0.0, tot = 0.0;
           for (int r = 0; r < R; ++r)
             for (int c = 0; c < R; ++c) {
@@ -454,13 +456,13 @@ __global__ void __launch_bounds__(kThreads) k_update_wave(const UpdateArgs a) {
               tot += w * w;
               if (r != c) offd += w * w;
             }
-          misc[4] = (offd <= 1e-30 * tot || !isfinite(offd)) ? 1.0 : 0.0;
+          misc[2] = (offd <= 1e-30 * tot || !isfinite(offd)) ? 1.0 : 0.0;
         }
-        wave_sync();
-        if (misc[4] != 0.0) break;
+        __syncthreads();
+        if (misc[2] != 0.0) break;
         for (int pp = 0; pp < R - 1; ++pp)
           for (int qq = pp + 1; qq < R; ++qq) {
-            if (lane == 0) {
+            if (t == 0) {
               const double apq = X[pp * ld + qq];
               double c = 1.0, sn = 0.0;
               if (apq != 0.0) {
@@ -469,93 +471,98 @@ __global__ void __launch_bounds__(kThreads) k_update_wave(const UpdateArgs a) {
                 c = 1.0 / sqrt(tt * tt + 1.0);
                 sn = tt * c;
               }
-              misc[1] = c;
-              misc[2] = sn;
+              misc[0] = c;
+              misc[1] = sn;
             }
-            wave_sync();
-            const double c = misc[1], sn = misc[2];
+            __syncthreads();
+            const double c = misc[0], sn = misc[1];
             if (sn != 0.0) {
-              if (lane < R) {
-                const double wp = X[lane * ld + pp], wq = X[lane * ld + qq];
-                X[lane * ld + pp] = c * wp - sn * wq;
-                X[lane * ld + qq] = sn * wp + c * wq;
-                const double vp = V[lane * ld + pp], vq = V[lane * ld + qq];
-                V[lane * ld + pp] = c * vp - sn * vq;
-                V[lane * ld + qq] = sn * vp + c * vq;
+              if (t < R) {
+                const double wp = X[t * ld + pp], wq = X[t * ld + qq];
+                X[t * ld + pp] = c * wp - sn * wq;
+                X[t * ld + qq] = sn * wp + c * wq;
+                const double vp = V[t * ld + pp], vq = V[t * ld + qq];
+                V[t * ld + pp] = c * vp - sn * vq;
+                V[t * ld + qq] = sn * vp + c * vq;
               }
-              wave_sync();
-              if (lane < R) {
-                const double wp = X[pp * ld + lane], wq = X[qq * ld + lane];
-                X[pp * ld + lane] = c * wp - sn * wq;
-                X[qq * ld + lane] = sn * wp + c * wq;
+              __syncthreads();
+              if (t < R) {
+                const double wp = X[pp * ld + t], wq = X[qq * ld + t];
+                X[pp * ld + t] = c * wp - sn * wq;
+                X[qq * ld + t] = sn * wp + c * wq;
               }
             }
-            wave_sync();
+            __syncthreads();
           }
       }
-      if (lane == 0) {
+      if (t == 0) {
         double wmax = 0.0;
         for (int r = 0; r < R; ++r) wmax = fmax(wmax, X[r * ld + r]);
         misc[3] = kPivotTolPerRank * R * wmax;
       }
-      wave_sync();
+      __syncthreads();
       const double cutoff = misc[3];
-      for (int e = lane; e < R * R; e += 64) {
+      for (int e = t; e < R * R; e += blockDim.x) {
         const int r = e / R, c = e % R;
         double acc = 0.0;
         for (int q = 0; q < R; ++q) {
           const double w = X[q * ld + q];
           if (w > cutoff) acc += V[r * ld + q] * (1.0 / w) * V[c * ld + q];
         }
-        Hinv[r * ld + c] = acc;
+        L[r * ld + c] = acc;
       }
-      wave_sync();
+      __syncthreads();
     }
 
-    // rows: U(i,:) = M(i,:) H^{-1} into LDS; the error's inner product
+    // U = M H^{-1} in LDS, and this thread's share of sum U .* M
     double inner = 0.0;
-    for (int e = lane; e < a.In * R; e += 64) {
+    for (int e = t; e < a.In * R; e += blockDim.x) {
       const int i = e / R, r = e % R;
-      const double* mrow = a.Mout + (int64_t)i * a.ldc + off;
-      double u = 0.0, m = 0.0;
-      if (i != zero_row) {
-        for (int q = 0; q < R; ++q) u += mrow[q] * Hinv[q * ld + r];
-        m = mrow[r];
-      }
-      rows[i * ld + r] = u;
-      inner += u * m;
+      const double* mrow = Ms + i * ld;
+      double u = 0.0;
+      for (int q = 0; q < R; ++q) u += mrow[q] * L[q * ld + r];
+      Us[i * ld + r] = u;
+      inner += u * mrow[r];
     }
-    wave_sync();
-    // column norms: lanes stride rows, fixed butterfly
-    for (int r = 0; r < R; ++r) {
-      double sq = 0.0;
-      for (int i = lane; i < a.In; i += 64) {
-        const double v = rows[i * ld + r];
-        sq += v * v;
+    red[t] = inner;
+    __syncthreads();
+    // column norms: one wave per column, lanes stride rows, fixed butterfly
+    {
+      const int wave = t >> 6, lane = t & 63, nw = blockDim.x >> 6;
+      for (int r = wave; r < R; r += nw) {
+        double sq = 0.0;
+        for (int i = lane; i < a.In; i += 64) {
+          const double v = Us[i * ld + r];
+          sq += v * v;
+        }
+        sq = wave_sum(sq);
+        if (lane == 0) lam[r] = sqrt(sq);
       }
-      sq = wave_sum(sq);
-      if (lane == 0) lam[r] = sqrt(sq);
     }
-    wave_sync();
-    // normalise, store U
-    for (int e = lane; e < a.In * R; e += 64) {
+    __syncthreads();
+    for (int e = t; e < a.In * R; e += blockDim.x) {
       const int i = e / R, r = e % R;
       const double l = lam[r];
-      double v = rows[i * ld + r];
+      double v = Us[i * ld + r];
       if (l > 0.0) v = v / l;
-      rows[i * ld + r] = v;
+      Us[i * ld + r] = v;
       a.U[(int64_t)i * a.ldc + off + r] = v;
     }
-    wave_sync();
-    // Gram of the normalised block, upper triangle then mirrored
+    __syncthreads();
+    // Gram of the normalised block: one wave per upper-triangle pair
     double* Gn = a.n == 0 ? a.G[0] : a.n == 1 ? a.G[1] : a.n == 2 ? a.G[2] : a.G[3];
     {
-      int r = 0, rem = 0;
+      const int wave = t >> 6, lane = t & 63, nw = blockDim.x >> 6;
       const int npairs = R * (R + 1) / 2;
-      for (int pr = 0; pr < npairs; ++pr) {
+      for (int pr = wave; pr < npairs; pr += nw) {
+        int r = 0, rem = pr;
+        while (rem >= R - r) {
+          rem -= R - r;
+          ++r;
+        }
         const int c = r + rem;
         double acc = 0.0;
-        for (int i = lane; i < a.In; i += 64) acc += rows[i * ld + r] * rows[i * ld + c];
+        for (int i = lane; i < a.In; i += 64) acc += Us[i * ld + r] * Us[i * ld + c];
         acc = wave_sum(acc);
         if (lane == 0) {
           Gn[goff + r * R + c] = acc;
@@ -563,23 +570,20 @@ __global__ void __launch_bounds__(kThreads) k_update_wave(const UpdateArgs a) {
           Gs[r * ld + c] = acc;
           Gs[c * ld + r] = acc;
         }
-        if (++rem >= R - r) {
-          rem = 0;
-          ++r;
-        }
       }
     }
-    if (lane < R) a.lambda[off + lane] = lam[lane];
-    inner = wave_sum(inner);
-    wave_sync();
-    if (lane == 0) {
+    if (t < R) a.lambda[off + t] = lam[t];
+    __syncthreads();
+    if (t == 0) {
       int32_t nst = st | (chol_ok ? 0 : JKC_ST_FALLBACK);
       if (a.last_mode) {
+        double in = 0.0;
+        for (int q = 0; q < (int)blockDim.x; ++q) in += red[q];
         double quad = 0.0;
         for (int r = 0; r < R; ++r)
           for (int c = 0; c < R; ++c) quad += lam[r] * H[r * ld + c] * Gs[r * ld + c] * lam[c];
         const double nt2 = a.normT2[k];
-        const double e = nt2 + quad - 2.0 * inner;
+        const double e = nt2 + quad - 2.0 * in;
         const double f = 1.0 - sqrt(fmax(e, 0.0)) / sqrt(nt2);
         const int it = a.iters[k] + 1;
         a.iters[k] = it;
@@ -592,7 +596,7 @@ __global__ void __launch_bounds__(kThreads) k_update_wave(const UpdateArgs a) {
       }
       a.status[k] = nst;
     }
-    wave_sync();
+    __syncthreads();
   }
 }
 
@@ -745,19 +749,17 @@ int grid_for(int64_t n) {
 
 }  // namespace
 
-int64_t update_wave_lds_doubles(int rmax, int rows) {
+int64_t update_lds_doubles(int rmax, int rows) {
   const int64_t ld = rmax + 1;
-  return 5 * rmax * ld + rmax + 8 + (int64_t)rows * ld;
+  return 5 * rmax * ld + rmax + 8 + kThreads + 2 * (int64_t)rows * ld;
 }
 
 hipError_t launch_update(const UpdateArgs& a, hipStream_t s) {
   if (a.mt.K <= 0) return hipSuccess;
-  if (a.wave_lds_doubles > 0 && a.waves_per_block > 0) {
-    const int wpb = a.waves_per_block;
-    int blocks = (a.mt.K + wpb - 1) / wpb;
-    if (blocks > 2048) blocks = 2048;
-    const size_t lds = (size_t)wpb * a.wave_lds_doubles * sizeof(double);
-    hipLaunchKernelGGL(k_update_wave, dim3(blocks), dim3(64 * wpb), lds, s, a);
+  if (a.lds_doubles > 0) {
+    int blocks = a.mt.K < 2048 ? a.mt.K : 2048;
+    hipLaunchKernelGGL(k_update_lds, dim3(blocks), dim3(kThreads),
+                       (size_t)a.lds_doubles * sizeof(double), s, a);
   } else {
     hipLaunchKernelGGL(k_update, dim3(persistent_grid(a.mt.K)), dim3(kThreads), 0, s, a);
   }
