@@ -33,7 +33,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sweeps", type=int, default=100)
-    ap.add_argument("--tune", action="store_true", help="autotune MTTKRP tilings before timing")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the MTTKRP tiling autotune (run before warmup, untimed)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-submodel GPU baseline")
     ap.add_argument("--plain-models", type=int, default=10)
@@ -89,7 +90,7 @@ def main():
     torch.cuda.synchronize()
 
     tiling = None
-    if args.tune:
+    if not args.no_tune:
         ctx = jk.JkCals(T, wl.dims, 0, wl.ranks, wl.left_out, init, precision=precision)
         ctx.tune(5)
         tiling = [ctx.describe(n) for n in range(N)]

@@ -109,14 +109,15 @@ struct Plan {
   }
 };
 
-// Upper bound on split-K chunks for a mode: enough to fill the chip when the
-// output is small, none when the output alone is large (its own tiles fill
-// the chip), and partials bounded to 64 MB or four output planes.
+// Upper bound on split-K chunks for a mode: enough to fill the chip twice
+// over when the output is small, none when the output alone is large (its
+// own tiles fill the chip), and partials bounded to 128 MB or four output
+// planes.
 int split_cap(int64_t rows, int64_t ldc, int64_t J) {
   const int64_t plane = rows * ldc * 8;
-  const int64_t budget = std::max<int64_t>(64ll << 20, 4 * plane);
+  const int64_t budget = std::max<int64_t>(128ll << 20, 4 * plane);
   int64_t s = budget / std::max<int64_t>(plane, 1);
-  s = std::min<int64_t>(s, 64);
+  s = std::min<int64_t>(s, 128);
   s = std::min<int64_t>(s, std::max<int64_t>(1, J / 64));
   return (int)std::max<int64_t>(s, 1);
 }
@@ -221,7 +222,8 @@ double model_cost(const Tiling& t, const ModeShape& s) {
   const int64_t nt = (s.ncols + t.bn() - 1) / t.bn();
   const double useful = (double)s.M * s.ncols;
   const double padded = (double)mt * t.bm() * nt * t.bn();
-  const double per_step = (double)t.tm * t.tn * (t.bk / 4) * (t.instr == 0 ? 1.45 : t.instr == 2 ? 0.25 : 1.0);
+  const int fam = t.instr & 7;
+  const double per_step = (double)t.tm * t.tn * (t.bk / 4) * (fam == 0 ? 1.45 : fam == 2 ? 0.25 : 1.0);
   const double hide = per_step / (per_step + 6.0);
   const double blocks = (double)mt * nt * t.splits;
   const double fill = std::min(1.0, blocks / (2.0 * kNumCU)) * std::min(1.0, (double)(t.wm * t.wn) / 4.0);
@@ -257,13 +259,15 @@ ModeShape mode_shape(const jkc_ctx* ctx, int n, int split_max) {
 
 std::string describe_tiling(const Tiling& t, int precision) {
   char buf[128];
-  snprintf(buf, sizeof(buf), "%s v%d wm%d wn%d tm%d tn%d bk%d s%d %s",
+  const int fam = t.instr & 7;
+  snprintf(buf, sizeof(buf), "%s v%d wm%d wn%d tm%d tn%d bk%d s%d %s%s",
            precision == JKC_SPLIT_BF16X3 ? "bf16x3" : precision == JKC_SPLIT_BF16X6 ? "bf16x6" : "f64",
            t.variant, t.wm, t.wn, t.tm, t.tn, t.bk, t.splits,
            precision != JKC_FP64 ? "mfma16x16x32bf16"
-           : t.instr == 2        ? "mfma4x4x4-strips"
-           : t.instr == 1        ? "mfma4x4x4-diagonal"
-                                 : "mfma16x16x4");
+           : fam == 2            ? "mfma4x4x4-strips"
+           : fam == 1            ? "mfma4x4x4-diagonal"
+                                 : "mfma16x16x4",
+           (precision == JKC_FP64 && (t.instr & 8)) ? "-interleaved" : "");
   return buf;
 }
 

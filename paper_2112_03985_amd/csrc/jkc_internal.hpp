@@ -33,7 +33,7 @@ struct Tiling {
   int variant = -1;   // index into the kernel table (precision specific)
   int wm = 0, wn = 0, tm = 0, tn = 0, bk = 0, instr = 0;
   int splits = 1;
-  int bm() const { return wm * tm * (instr == 2 ? 4 : 16); }
+  int bm() const { return wm * tm * ((instr & 7) == 2 ? 4 : 16); }
   int bn() const { return wn * tn * 16; }
 };
 
@@ -60,7 +60,8 @@ struct MttkrpArgs {
 struct MttkrpVariant {
   int wm, wn, tm, tn, bk;
   hipError_t (*launch)(const MttkrpArgs&, hipStream_t);
-  int instr;   // matrix instruction family (kernel specific)
+  int instr;   // matrix instruction family (kernel specific, low 3 bits) |
+               // 8 when the step uses the interleaved instruction schedule
 };
 const std::vector<MttkrpVariant>& mttkrp_f64_variants();
 const std::vector<MttkrpVariant>& mttkrp_split_variants();    // two bf16 terms

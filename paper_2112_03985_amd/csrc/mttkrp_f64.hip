@@ -34,6 +34,7 @@
 //      of A and block b columns 4b..4b+3 of a 16-column group, so one
 //      instruction is a 4 x 16 x 4 step and tiles need only multiples of 4
 //      rows (no padding of 100- or 200-row modes to 16).
+// INSTR + 8 selects the interleaved step schedule (see the main loop).
 // Partials of the K chunks are summed later in a fixed order, so results are
 // bitwise repeatable for a fixed tiling.
 #include <type_traits>
@@ -46,7 +47,6 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int kPad = 8;  // LDS row padding (doubles)
 constexpr int kXcds = 8;  // accelerator complex dies on MI355X
 
 // Lane layout of v_mfma_f64_4x4x4 (4 blocks), measured on gfx950: lane l
@@ -88,23 +88,33 @@ struct ColWalker {
   }
 };
 
-template <int WM, int WN, int TM, int TN, int BK, int INSTR>
+template <int WM, int WN, int TM, int TN, int BK, int INSTR, int NO, bool F32>
 __global__ void __launch_bounds__(64 * WM * WN)
 k_mttkrp_f64(const MttkrpArgs a) {
   constexpr int NT = 64 * WM * WN;
-  constexpr int RPT = INSTR == 2 ? 4 : 16;   // rows per matrix-core tile
+  constexpr int FAM = INSTR & 7;             // matrix instruction family
+  constexpr bool SCHED = (INSTR & 8) != 0;   // interleaved step schedule
+  constexpr int RPT = FAM == 2 ? 4 : 16;     // rows per matrix-core tile
   constexpr int BM = WM * TM * RPT;
-  constexpr int BMP = (BM + 15) / 16 * 16;    // rows staged in LDS
+  // rows staged in LDS: a multiple of 16, and of the rows one K index of a
+  // step spreads over the block's threads
+  constexpr int RQ = NT / BK > 16 ? NT / BK : 16;
+  constexpr int BMP = (BM + RQ - 1) / RQ * RQ;
   constexpr int BN = WN * TN * 16;
-  constexpr int LDA = BMP + kPad;
-  constexpr int LDB = BN + kPad;
+  // Row pitches in LDS (doubles), chosen modulo 32 so that the fragment
+  // reads and the staging writes spread over the 64 four-byte banks: A rows
+  // at 20 (mod 32) for the row-strip reads (4 rows x 4 doubles) and the
+  // column-walk writes, 24 for 16-double row reads; B rows at 8.
+  constexpr int LDA = BMP + ((FAM == 2 ? 20 : 24) - BMP % 32 + 32) % 32;
+  constexpr int LDB = BN + (8 - BN % 32 + 32) % 32;
   constexpr int VA = BMP * BK / NT;  // A elements per thread per step (one column)
   constexpr int VB = BN * BK / NT;   // B elements per thread per step (one column)
   static_assert(BK % 4 == 0, "BK");
   static_assert(VA >= 1 && VA * NT == BMP * BK, "A tile must split evenly over threads");
   static_assert(VB >= 1 && VB * NT == BN * BK, "B tile must split evenly over threads");
   static_assert(BMP % VA == 0 && BN % VB == 0, "vector width");
-  using AccT = typename std::conditional<INSTR == 2, double, v4d>::type;
+  static_assert(VB == 1 || VB % 2 == 0, "B is staged in pairs of columns");
+  using AccT = typename std::conditional<FAM == 2, double, v4d>::type;
 
   __shared__ __attribute__((aligned(16))) double As[2][BK][LDA];
   __shared__ __attribute__((aligned(16))) double Bs[2][BK][LDB];
@@ -132,13 +142,23 @@ k_mttkrp_f64(const MttkrpArgs a) {
   const int64_t kend = min(kbeg + a.kchunk, a.J);
   const int nsteps = kend > kbeg ? (int)((kend - kbeg + BK - 1) / BK) : 0;
 
-  // Thread roles.  A: mode with unit stride (rows contiguous in memory) ->
-  // threads run along the rows of one column; otherwise along the columns.
+  // Thread roles.  A (BMP x BK slice of the unfolding): for a mode with unit
+  // stride (rows contiguous in memory) threads run along the rows of one
+  // column, otherwise along the columns of one row; a thread's VA elements
+  // are interleaved with its neighbours' (row gA + sA * v), so each load and
+  // each LDS write of a wavefront covers contiguous addresses.  B (BK x BN
+  // Khatri-Rao slice): threads run along the columns of one K index, in
+  // pairs of columns interleaved the same way (column 2 gB + 2 GB u).
   const bool m_fast = a.stride_n == 1;
-  const int kA = m_fast ? tid / (BMP / VA) : tid % BK;
-  const int iA = m_fast ? (tid % (BMP / VA)) * VA : (tid / BK) * VA;
-  const int kB = tid % BK;
-  const int cB = (tid / BK) * VB;
+  constexpr int GA = BMP / VA;      // threads per A column when m_fast
+  constexpr int GK = NT / BK;       // threads per A row otherwise
+  const int kA = m_fast ? tid / GA : tid % BK;
+  const int gA = m_fast ? tid % GA : tid / BK;
+  const int sA = m_fast ? GA : GK;
+  constexpr int PB = VB == 1 ? 1 : 2;  // columns per B chunk
+  constexpr int GB = BN / VB;          // threads per K index of B
+  const int kB = tid / GB;
+  const int gB = tid % GB;
 
   ColWalker wA, wB;
   wA.init(a, kbeg + kA);
@@ -147,50 +167,84 @@ k_mttkrp_f64(const MttkrpArgs a) {
   const double* __restrict__ Tf64 = static_cast<const double*>(a.T);
   const float* __restrict__ Tf32 = static_cast<const float*>(a.T);
 
-  double ra[VA];
-  double rb[kMaxOrder - 1][VB];
+  // Registers of the step in flight.  Loads are unconditional at a clamped
+  // address; which values are real is kept in amask / bmask and applied when
+  // the step is stored, so no load result is consumed (waited for) before
+  // the matrix-core work of the current step has been issued.
+  using TT = typename std::conditional<F32, float, double>::type;
+  TT ra[VA];
+  double rb[NO][VB];
+  uint32_t amask = 0;
+  uint32_t bmask = 0;
 
   auto load_step = [&]() {
     const bool va = wA.j < kend;
-    const int64_t toffA = wA.toff(a);
+    const int64_t toffA = va ? wA.toff(a) : 0;
+    amask = 0;
 #pragma unroll
     for (int v = 0; v < VA; ++v) {
-      const int row = i0 + iA + v;
-      double x = 0.0;
-      if (va && iA + v < BM && row < a.M) {
-        const int64_t addr = toffA + (int64_t)row * a.stride_n;
-        x = a.t_is_f32 ? (double)Tf32[addr] : Tf64[addr];
-      }
-      ra[v] = x;
+      const int r = gA + sA * v;
+      const int row = i0 + r;
+      const bool ok = va && r < BM && row < a.M;
+      amask |= (uint32_t)ok << v;
+      const int64_t addr = ok ? toffA + (int64_t)row * a.stride_n : 0;
+      ra[v] = F32 ? Tf32[addr] : Tf64[addr];
     }
-    const bool vb = wB.j < kend;
+    // Columns come in pairs (ldc is even), each pair wholly inside the
+    // factor rows or wholly past them; the columns between ncols and ldc
+    // hold zeros.
+    const bool kok = wB.j < kend;
+    bmask = 0;
 #pragma unroll
-    for (int q = 0; q < kMaxOrder - 1; ++q) {
-      if (q < a.nother) {
-        const double* __restrict__ urow = a.oU[q] + (int64_t)wB.idx[q] * a.ldc;
+    for (int u = 0; u < VB / PB; ++u) {
+      const int col = c0 + PB * (gB + GB * u);
+      bmask |= (uint32_t)(kok && col < a.ldc) << u;
+    }
 #pragma unroll
-        for (int v = 0; v < VB; ++v) {
-          const int col = c0 + cB + v;
-          rb[q][v] = (vb && col < a.ncols) ? urow[col] : 0.0;
+    for (int q = 0; q < NO; ++q) {
+      const double* __restrict__ urow = a.oU[q] + (int64_t)(kok ? wB.idx[q] : 0u) * a.ldc;
+#pragma unroll
+      for (int u = 0; u < VB / PB; ++u) {
+        const int col = c0 + PB * (gB + GB * u);
+        const int cc = (bmask >> u) & 1u ? col : 0;
+        if constexpr (PB == 2) {
+          const double2 x = *reinterpret_cast<const double2*>(urow + cc);
+          rb[q][2 * u] = x.x;
+          rb[q][2 * u + 1] = x.y;
+        } else {
+          rb[q][u] = urow[cc];
         }
       }
     }
   };
   auto store_step = [&](int buf) {
+    // Empty asm statements pin the first use of the loaded registers here:
+    // the wait on global memory and every product come after this point.
 #pragma unroll
-    for (int v = 0; v < VA; ++v) As[buf][kA][iA + v] = ra[v];
+    for (int v = 0; v < VA; ++v) asm volatile("" : "+v"(ra[v]));
 #pragma unroll
-    for (int v = 0; v < VB; ++v) {
-      // product from the highest mode down (the listing order of Eq. (1))
-      double x = 0.0;
-      bool first = true;
+    for (int q = 0; q < NO; ++q)
 #pragma unroll
-      for (int q = kMaxOrder - 2; q >= 0; --q)
-        if (q < a.nother) {
-          x = first ? rb[q][v] : x * rb[q][v];
-          first = false;
-        }
-      Bs[buf][kB][cB + v] = x;
+      for (int v = 0; v < VB; ++v) asm volatile("" : "+v"(rb[q][v]));
+#pragma unroll
+    for (int v = 0; v < VA; ++v)
+      As[buf][kA][gA + sA * v] = (amask >> v) & 1u ? (double)ra[v] : 0.0;
+#pragma unroll
+    for (int u = 0; u < VB / PB; ++u) {
+      double x[PB];
+#pragma unroll
+      for (int p = 0; p < PB; ++p) {
+        // product from the highest mode down (the listing order of Eq. (1))
+        double y = rb[NO - 1][PB * u + p];
+#pragma unroll
+        for (int q = NO - 2; q >= 0; --q) y *= rb[q][PB * u + p];
+        x[p] = (bmask >> u) & 1u ? y : 0.0;
+      }
+      double* dst = &Bs[buf][kB][PB * (gB + GB * u)];
+      if constexpr (PB == 2)
+        *reinterpret_cast<double2*>(dst) = make_double2(x[0], x[1]);
+      else
+        dst[0] = x[0];
     }
   };
 
@@ -211,60 +265,125 @@ k_mttkrp_f64(const MttkrpArgs a) {
   const int b4 = (lane >> 2) & 3;   // 4x4x4 block of this lane
   const int e4 = lane & 3;
   const int kq4 = lane >> 4;
+
+  // Matrix-core operand fragments, double-buffered in registers: the
+  // fragments of group g+1 are read from LDS while the matrix cores work on
+  // group g.
+  constexpr int FB = FAM == 1 ? 4 * TN : TN;
+  constexpr int G = BK / 4;                        // groups of 4 K per step
+  constexpr int NMF = TM * TN * (FAM == 1 ? 4 : 1);
+  constexpr int NRD = TM + FB;
+  double fa[2][TM], fb[2][FB];
+  auto read_frag = [&](int buf, int kk, int slot) {
+    if constexpr (FAM == 2) {
+      // row strips: every block gets the same 4 rows of A (same LDS
+      // addresses), block b the columns 4b..4b+3 of each 16-column group
+#pragma unroll
+      for (int x = 0; x < TM; ++x) fa[slot][x] = As[buf][kk + kq4][wm * TM * 4 + x * 4 + e4];
+#pragma unroll
+      for (int y = 0; y < TN; ++y)
+        fb[slot][y] = Bs[buf][kk + kq4][wn * TN * 16 + y * 16 + 4 * b4 + e4];
+    } else if constexpr (FAM == 0) {
+#pragma unroll
+      for (int x = 0; x < TM; ++x) fa[slot][x] = As[buf][kk + blk][wm * TM * 16 + x * 16 + o16];
+#pragma unroll
+      for (int y = 0; y < TN; ++y) fb[slot][y] = Bs[buf][kk + blk][wn * TN * 16 + y * 16 + o16];
+    } else {
+#pragma unroll
+      for (int x = 0; x < TM; ++x)
+        fa[slot][x] = As[buf][kk + kq4][wm * TM * 16 + x * 16 + 4 * b4 + e4];
+#pragma unroll
+      for (int y = 0; y < TN; ++y)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          fb[slot][4 * y + q] = Bs[buf][kk + kq4][wn * TN * 16 + y * 16 + 4 * ((b4 + q) & 3) + e4];
+    }
+  };
+  auto mfma_group = [&](int slot) {
+#pragma unroll
+    for (int x = 0; x < TM; ++x)
+#pragma unroll
+      for (int y = 0; y < TN; ++y) {
+        if constexpr (FAM == 2)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_4x4x4f64(fa[slot][x], fb[slot][y], acc[x][y], 0, 0, 0);
+        else if constexpr (FAM == 0)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[slot][x], fb[slot][y], acc[x][y], 0, 0, 0);
+        else
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            acc[x][y][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(fa[slot][x], fb[slot][4 * y + q],
+                                                              acc[x][y][q], 0, 0, 0);
+      }
+  };
+
+  // One K step = G groups of matrix-core work.  Loads and the store of the
+  // next step run unconditionally (past the end of the chunk they fetch
+  // clamped addresses and store zeros into the idle buffer), which keeps the
+  // step free of branches; the store goes into the other LDS buffer, free
+  // since the last barrier, before the final group.
+  //
+  // Interleaved schedule (SCHED): each group is a scheduling region of its
+  // own in which the step's memory work is interleaved with the matrix
+  // instructions by scheduling-group directives (one global load, one LDS
+  // read, or one LDS write with its arithmetic between matrix instructions)
+  // and the fragments of group g+1 are read while group g computes.
+  // Otherwise the compiler schedules each group; scheduling barriers only
+  // keep the loads at the head of the step and the store before the last
+  // group.
   for (int s = 0; s < nsteps; ++s) {
     const int buf = s & 1;
-    const bool more = s + 1 < nsteps;
-    if (more) {
+    if constexpr (SCHED) {
+      read_frag(buf, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
       wA.advance(a, BK);
       wB.advance(a, BK);
       load_step();
-    }
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      double av[TM], bv[TN];
-      if constexpr (INSTR == 2) {
-        // row strips: every block gets the same 4 rows of A (same LDS
-        // addresses), block b the columns 4b..4b+3 of each 16-column group
+      for (int g = 0; g < G; ++g) {
+        const int cur = g & 1;
+        if (g + 1 < G) read_frag(buf, 4 * (g + 1), cur ^ 1);
+        else store_step(buf ^ 1);
+        mfma_group(cur);
+        if (g == 0) {
 #pragma unroll
-        for (int x = 0; x < TM; ++x) av[x] = As[buf][kk + kq4][wm * TM * 4 + x * 4 + e4];
+          for (int i = 0; i < VA + NO * (VB / PB); ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // global load
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // matrix
+          }
+        }
+        if (g + 1 < G) {
 #pragma unroll
-        for (int y = 0; y < TN; ++y) bv[y] = Bs[buf][kk + kq4][wn * TN * 16 + y * 16 + 4 * b4 + e4];
+          for (int i = 0; i < NRD; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // matrix
+          }
+        } else {
 #pragma unroll
-        for (int x = 0; x < TM; ++x)
+          for (int i = 0; i < VA + VB / PB; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x002, 2 * NO, 0);   // products, selects
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);       // LDS write
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);       // matrix
+          }
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+      wA.advance(a, BK);
+      wB.advance(a, BK);
+      load_step();
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int y = 0; y < TN; ++y)
-            acc[x][y] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
-      } else if constexpr (INSTR == 0) {
-#pragma unroll
-        for (int x = 0; x < TM; ++x) av[x] = As[buf][kk + blk][wm * TM * 16 + x * 16 + o16];
-#pragma unroll
-        for (int y = 0; y < TN; ++y) bv[y] = Bs[buf][kk + blk][wn * TN * 16 + y * 16 + o16];
-#pragma unroll
-        for (int x = 0; x < TM; ++x)
-#pragma unroll
-          for (int y = 0; y < TN; ++y)
-            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
-      } else {
-        double bq[TN][4];
-#pragma unroll
-        for (int x = 0; x < TM; ++x)
-          av[x] = As[buf][kk + kq4][wm * TM * 16 + x * 16 + 4 * b4 + e4];
-#pragma unroll
-        for (int y = 0; y < TN; ++y)
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            bq[y][q] = Bs[buf][kk + kq4][wn * TN * 16 + y * 16 + 4 * ((b4 + q) & 3) + e4];
-#pragma unroll
-        for (int x = 0; x < TM; ++x)
-#pragma unroll
-          for (int y = 0; y < TN; ++y)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              acc[x][y][q] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[x], bq[y][q], acc[x][y][q], 0, 0, 0);
-        (void)bv;
+      for (int g = 0; g < G; ++g) {
+        if (g == G - 1) {
+          __builtin_amdgcn_sched_barrier(0);
+          store_step(buf ^ 1);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        read_frag(buf, 4 * g, 0);
+        mfma_group(0);
       }
     }
-    if (more) store_step(buf ^ 1);
     __syncthreads();
   }
 
@@ -272,7 +391,7 @@ k_mttkrp_f64(const MttkrpArgs a) {
   // column l%16 of its tile.  4x4x4: element q holds row 4*b + l/16 and
   // column 4*((b+q) mod 4) + (l mod 4), b = (l/4) mod 4.
   double* __restrict__ out = a.partial + (int64_t)split * a.M * a.ldc;
-  if constexpr (INSTR == 2) {
+  if constexpr (FAM == 2) {
     // row strip x, group y: lane holds row 4x + l/16, column 16y + 4b + l%4
 #pragma unroll
     for (int x = 0; x < TM; ++x)
@@ -291,7 +410,7 @@ k_mttkrp_f64(const MttkrpArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         int rr, cc;
-        if (INSTR == 0) {
+        if (FAM == 0) {
           rr = 4 * r + blk;
           cc = o16;
         } else {
@@ -305,10 +424,25 @@ k_mttkrp_f64(const MttkrpArgs a) {
   }
 }
 
+template <int WM, int WN, int TM, int TN, int BK, int INSTR, int NO, bool F32>
+void launch_one(const MttkrpArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_mttkrp_f64<WM, WN, TM, TN, BK, INSTR, NO, F32>),
+                     dim3(a.mtiles * a.ntiles * a.splits), dim3(64 * WM * WN), 0, s, a);
+}
+
+// One instantiation per (number of other modes, tensor element type), so
+// that the load and product loops are fully unrolled without branches.
 template <int WM, int WN, int TM, int TN, int BK, int INSTR>
 hipError_t launch_f64(const MttkrpArgs& a, hipStream_t s) {
-  dim3 grid(a.mtiles * a.ntiles * a.splits);
-  hipLaunchKernelGGL((k_mttkrp_f64<WM, WN, TM, TN, BK, INSTR>), grid, dim3(64 * WM * WN), 0, s, a);
+  switch (a.nother * 2 + (a.t_is_f32 ? 1 : 0)) {
+    case 2: launch_one<WM, WN, TM, TN, BK, INSTR, 1, false>(a, s); break;
+    case 3: launch_one<WM, WN, TM, TN, BK, INSTR, 1, true>(a, s); break;
+    case 4: launch_one<WM, WN, TM, TN, BK, INSTR, 2, false>(a, s); break;
+    case 5: launch_one<WM, WN, TM, TN, BK, INSTR, 2, true>(a, s); break;
+    case 6: launch_one<WM, WN, TM, TN, BK, INSTR, 3, false>(a, s); break;
+    case 7: launch_one<WM, WN, TM, TN, BK, INSTR, 3, true>(a, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -330,15 +464,23 @@ const std::vector<MttkrpVariant>& mttkrp_f64_variants() {
       JKC_F64_VARIANT(1, 4, 16, 2, 16, 2),  // 64 x 128
       JKC_F64_VARIANT(2, 2, 32, 1, 16, 2),  // 256 x 32
       JKC_F64_VARIANT(2, 2, 2, 2, 16, 1),   // 64 x 64, 4x4x4 diagonal
-      JKC_F64_VARIANT(2, 2, 2, 4, 16, 1),   // 64 x 128
       JKC_F64_VARIANT(2, 2, 4, 2, 16, 1),   // 128 x 64
-      JKC_F64_VARIANT(1, 4, 7, 2, 16, 1),   // 112 x 128
-      JKC_F64_VARIANT(2, 2, 1, 1, 32, 1),   // 32 x 32
-      JKC_F64_VARIANT(4, 1, 1, 1, 32, 1),   // 64 x 16
-      JKC_F64_VARIANT(4, 1, 2, 1, 32, 1),   // 128 x 16
       JKC_F64_VARIANT(2, 2, 2, 2, 16, 0),   // 64 x 64, 16x16x4
       JKC_F64_VARIANT(2, 2, 4, 2, 16, 0),   // 128 x 64
       JKC_F64_VARIANT(1, 4, 7, 2, 16, 0),   // 112 x 128
+      JKC_F64_VARIANT(2, 4, 13, 2, 32, 2),  // 104 x 128, 8 wavefronts, BK 32
+      JKC_F64_VARIANT(2, 2, 13, 4, 32, 2),  // 104 x 128, BK 32
+      // interleaved schedule
+      JKC_F64_VARIANT(1, 4, 7, 2, 16, 8),   // 112 x 128, 16x16x4
+      JKC_F64_VARIANT(2, 2, 4, 2, 16, 8),   // 128 x 64, 16x16x4
+      JKC_F64_VARIANT(2, 2, 13, 4, 16, 10), // 104 x 128, strips
+      JKC_F64_VARIANT(2, 2, 13, 2, 16, 10), // 104 x 64, strips
+      JKC_F64_VARIANT(2, 4, 13, 2, 32, 10), // 104 x 128, 8 wavefronts, BK 32
+      JKC_F64_VARIANT(2, 4, 13, 2, 16, 10), // 104 x 128, 8 wavefronts
+      JKC_F64_VARIANT(4, 2, 7, 4, 32, 10),  // 112 x 128, 8 wavefronts, BK 32
+      JKC_F64_VARIANT(4, 2, 13, 2, 32, 10), // 208 x 64, 8 wavefronts, BK 32
+      JKC_F64_VARIANT(2, 4, 13, 4, 16, 10), // 104 x 256, 8 wavefronts
+      JKC_F64_VARIANT(2, 4, 4, 2, 16, 8),   // 128 x 128, 8 wavefronts, 16x16x4
   };
   return v;
 }

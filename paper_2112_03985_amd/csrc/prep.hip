@@ -167,8 +167,19 @@ __global__ void k_reduce(const double* partial, int32_t splits, int32_t rows, in
     const int64_t i = e / ncols;
     const int c = (int)(e % ncols);
     const int64_t at = i * ldc + c;
+    // Loads of kBatch partials are issued together (they are independent),
+    // the additions still run in ascending split order.
+    constexpr int kBatch = 16;
     double s = 0.0;
-    for (int sp = 0; sp < splits; ++sp) s += partial[sp * plane + at];
+    int sp = 0;
+    for (; sp + kBatch <= splits; sp += kBatch) {
+      double v[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) v[u] = partial[(int64_t)(sp + u) * plane + at];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) s += v[u];
+    }
+    for (; sp < splits; ++sp) s += partial[(int64_t)sp * plane + at];
     if (zero_rows && colp[c] == (int)i) s = 0.0;
     out[i * ldo + c] = s;
   }
