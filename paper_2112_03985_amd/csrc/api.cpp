@@ -207,8 +207,8 @@ Tiling make_tiling(const std::vector<MttkrpVariant>& vars, int v, const ModeShap
 
 int default_splits(const Tiling& t, const ModeShape& s) {
   const int64_t tiles = ((s.M + t.bm() - 1) / t.bm()) * ((s.ncols + t.bn() - 1) / t.bn());
-  // aim for two resident blocks per compute unit
-  const int64_t want_blocks = 2 * kNumCU;
+  // aim for two resident blocks per compute unit (one of 8 wavefronts)
+  const int64_t want_blocks = (t.wm * t.wn >= 8 ? 1 : 2) * kNumCU;
   int64_t s_ = (want_blocks + tiles - 1) / tiles;
   s_ = std::min<int64_t>(s_, std::max<int64_t>(1, s.J / (8 * t.bk)));
   return (int)std::max<int64_t>(1, std::min<int64_t>(s_, s.split_max));
@@ -224,9 +224,13 @@ double model_cost(const Tiling& t, const ModeShape& s) {
   const double padded = (double)mt * t.bm() * nt * t.bn();
   const int fam = t.instr & 7;
   const double per_step = (double)t.tm * t.tn * (t.bk / 4) * (fam == 0 ? 1.45 : fam == 2 ? 0.25 : 1.0);
-  const double hide = per_step / (per_step + 6.0);
+  // the interleaved schedule hides more of the fixed cost; an 8-wavefront
+  // block keeps two wavefronts on every SIMD
+  const double hide = per_step / (per_step + ((t.instr & 8) ? 3.0 : 6.0));
   const double blocks = (double)mt * nt * t.splits;
-  const double fill = std::min(1.0, blocks / (2.0 * kNumCU)) * std::min(1.0, (double)(t.wm * t.wn) / 4.0);
+  const double per_cu = t.wm * t.wn >= 8 ? 1.0 : 2.0;
+  const double fill = std::min(1.0, blocks / (per_cu * kNumCU)) * std::min(1.0, (double)(t.wm * t.wn) / 4.0) *
+                      (t.wm * t.wn >= 8 ? 1.1 : 1.0);
   double cost = (padded / useful) / (hide * std::max(fill, 1e-3));
   if (t.splits > 1) cost *= 1.0 + 96.0 * t.splits / (double)s.J;
   return cost;

@@ -34,6 +34,20 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Sum of one value per thread in a fixed order: butterfly within each
+// wavefront, then the wavefront sums in ascending order; every thread gets
+// the result.  scratch needs blockDim.x / 64 doubles; the call synchronises
+// the block (and leaves scratch free again).
+__device__ inline double block_sum(double v, double* scratch) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += scratch[q];
+  __syncthreads();
+  return s;
+}
+
 // H for model k: product of the other modes' Gram blocks in ascending mode
 // order (the oracle's order).
 __device__ void build_h(const double* G0, const double* G1, const double* G2, const double* G3,
@@ -290,8 +304,7 @@ __global__ void __launch_bounds__(kThreads) k_update(const UpdateArgs a) {
       jacobi_pinv(H, Wj, Vj, Hp, R, s_cs);
 
     const double inner = row_pass(a.Mout, a.U, a.In, a.ldc, off, R, zero_row, Hp);
-    s_red[threadIdx.x] = inner;
-    __syncthreads();
+    const double in_all = block_sum(inner, s_red);
 
     column_norms(a.U, a.In, a.ldc, off, R, s_lam);
     __syncthreads();
@@ -312,8 +325,7 @@ __global__ void __launch_bounds__(kThreads) k_update(const UpdateArgs a) {
     if (threadIdx.x == 0) {
       int32_t nst = st | (chol_ok ? 0 : JKC_ST_FALLBACK);
       if (a.last_mode) {
-        double in = 0.0;
-        for (int t = 0; t < (int)blockDim.x; ++t) in += s_red[t];
+        const double in = in_all;
         double quad = 0.0;
         for (int r = 0; r < R; ++r)
           for (int s = 0; s < R; ++s) quad += s_lam[r] * H[r][s] * Gs[r][s] * s_lam[s];
@@ -524,8 +536,7 @@ __global__ void __launch_bounds__(kThreads) k_update_lds(const UpdateArgs a) {
       Us[i * ld + r] = u;
       inner += u * mrow[r];
     }
-    red[t] = inner;
-    __syncthreads();
+    const double in_all = block_sum(inner, red);
     // column norms: one wave per column, lanes stride rows, fixed butterfly
     {
       const int wave = t >> 6, lane = t & 63, nw = blockDim.x >> 6;
@@ -577,8 +588,7 @@ __global__ void __launch_bounds__(kThreads) k_update_lds(const UpdateArgs a) {
     if (t == 0) {
       int32_t nst = st | (chol_ok ? 0 : JKC_ST_FALLBACK);
       if (a.last_mode) {
-        double in = 0.0;
-        for (int q = 0; q < (int)blockDim.x; ++q) in += red[q];
+        const double in = in_all;
         double quad = 0.0;
         for (int r = 0; r < R; ++r)
           for (int c = 0; c < R; ++c) quad += lam[r] * H[r * ld + c] * Gs[r * ld + c] * lam[c];
@@ -641,11 +651,9 @@ __global__ void __launch_bounds__(kThreads) k_grad(const GradArgs a) {
       a.grad[(int64_t)i * a.ldc + off + r] = g;
       inner += urow[r] * m;
     }
-    s_red[threadIdx.x] = inner;
-    __syncthreads();
+    const double in_all = block_sum(inner, s_red);
     if (a.last_mode && threadIdx.x == 0) {
-      double in = 0.0;
-      for (int t = 0; t < (int)blockDim.x; ++t) in += s_red[t];
+      const double in = in_all;
       const double* Gn = (a.n == 0 ? a.Gp[0] : a.n == 1 ? a.Gp[1] : a.n == 2 ? a.Gp[2] : a.Gp[3]) + goff;
       double quad = 0.0;
       for (int r = 0; r < R; ++r)
