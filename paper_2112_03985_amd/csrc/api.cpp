@@ -70,16 +70,20 @@ struct Plan {
   std::vector<Item> items;
   int64_t total = 0;
 
+  // row pitch of the split-precision unfolded copy of mode n
+  int64_t split_ld(int n) const { return align_up(P / dims[n], 8); }
+
   void layout() {
     items.clear();
     const int64_t es = tensor_f32 ? 4 : 8;
     int64_t tbytes = 0;
-    if (precision == JKC_SPLIT_BF16X3)
-      tbytes = 2 * P * 2;
-    else if (precision == JKC_SPLIT_BF16X6)
-      tbytes = 3 * P * 2;
-    else if (copy_tensor)
+    if (precision != JKC_FP64) {
+      // one unfolded copy per mode (rows padded to 8 columns), nterm planes each
+      const int nterm = precision == JKC_SPLIT_BF16X6 ? 3 : 2;
+      for (int n = 0; n < N; ++n) tbytes += (int64_t)nterm * dims[n] * split_ld(n) * 2;
+    } else if (copy_tensor) {
       tbytes = P * es;
+    }
     items.push_back({"tensor", tbytes});
     for (int n = 0; n < N; ++n) items.push_back({"U", dims[n] * ldc * 8});
     for (int n = 0; n < N; ++n) items.push_back({"G", gsize * 8});
@@ -366,8 +370,9 @@ jkc_status enqueue_mttkrp(jkc_ctx* ctx, int n, const Tiling& t) {
   if (t.variant < 0 || t.variant >= (int)vars.size()) return fail(JKC_ESTATE, "no tiling");
   MttkrpArgs a{};
   if (ctx->nterm > 0) {
-    a.T = ctx->T_planes;
-    a.plane = ctx->P;
+    a.T = ctx->T_planes + ctx->tp_off[n];
+    a.plane = ctx->dims[n] * ctx->tp_ld[n];
+    a.ldt = ctx->tp_ld[n];
   } else {
     a.T = ctx->T;
     a.plane = 0;
@@ -734,7 +739,14 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
   if (pl.precision != JKC_FP64) {
     c.nterm = pl.precision == JKC_SPLIT_BF16X6 ? 3 : 2;
     c.T_planes = static_cast<uint16_t*>(tbuf);
-    JKC_HIP(launch_split_tensor(tensor, pl.tensor_f32, c.T_planes, c.nterm, pl.P, st));
+    int64_t off = 0;
+    for (int n = 0; n < pl.N; ++n) {
+      c.tp_off[n] = off;
+      c.tp_ld[n] = pl.split_ld(n);
+      JKC_HIP(launch_split_unfold(tensor, pl.tensor_f32, pl.N, pl.dims, n, c.tp_ld[n], c.nterm,
+                                  c.T_planes + off, st));
+      off += (int64_t)c.nterm * pl.dims[n] * c.tp_ld[n];
+    }
   } else if (pl.copy_tensor) {
     JKC_HIP(launch_copy_tensor(tensor, pl.tensor_f32, tbuf, pl.P, st));
     c.T = tbuf;

@@ -49,6 +49,7 @@ struct MttkrpArgs {
   int32_t M;                // I_n (output rows)
   int64_t J;                // columns of the unfolding
   int64_t kchunk;           // K elements per split (multiple of BK)
+  int64_t ldt;              // split paths: row pitch of the unfolded planes
   int32_t ldc;              // leading dimension of factors and partials
   int32_t ncols;            // columns to produce (<= ldc)
   int32_t mtiles, ntiles;
@@ -124,8 +125,12 @@ hipError_t launch_reduce(const double* partial, int32_t splits, int32_t rows,
 // Preparation kernels.
 hipError_t launch_copy_tensor(const void* src, int32_t src_f32, void* dst,
                               int64_t count, hipStream_t s);
-hipError_t launch_split_tensor(const void* src, int32_t src_f32, uint16_t* planes,
-                               int32_t nterm, int64_t count, hipStream_t s);
+// Split-precision tensor copy of one mode: the mode-n unfolding (Eq. (3))
+// stored row-major with row pitch ldt (>= P / I_n, a multiple of 8, padding
+// zero), as nterm bfloat16 planes of I_n * ldt elements.
+hipError_t launch_split_unfold(const void* src, int32_t src_f32, int32_t N, const int64_t* dims,
+                               int32_t n, int64_t ldt, int32_t nterm, uint16_t* planes,
+                               hipStream_t s);
 hipError_t launch_slice_norms(const void* T, int32_t t_f32, int64_t inner,
                               int32_t I, int64_t outer, double* partial,
                               int32_t chunks, double* s_out, hipStream_t s);
@@ -189,8 +194,10 @@ struct jkc_ctx {
 
   // device buffers (all inside the caller's workspace)
   const void* T = nullptr;       // FP64 path tensor (f64 or f32)
-  uint16_t* T_planes = nullptr;  // split paths: nterm bf16 planes of P elements
+  uint16_t* T_planes = nullptr;  // split paths: per mode, nterm bf16 planes
   int32_t nterm = 0;
+  int64_t tp_off[jkc::kMaxOrder] = {0, 0, 0, 0};   // element offset of mode n's planes
+  int64_t tp_ld[jkc::kMaxOrder] = {0, 0, 0, 0};    // their row pitch
   double* U[jkc::kMaxOrder] = {nullptr, nullptr, nullptr, nullptr};
   double* G[jkc::kMaxOrder] = {nullptr, nullptr, nullptr, nullptr};
   double* Mbuf = nullptr;        // [max I_n][ldc]

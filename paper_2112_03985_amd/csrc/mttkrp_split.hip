@@ -19,6 +19,30 @@
 // cancellation in the MTTKRP sums), i.e. a few 1e-6 on data without
 // cancellation and about 1e-5 when the sums cancel by half; with three
 // terms it is ~2^-23 times that ratio.
+//
+// Layout.  For the split paths the tensor is held once per mode as that
+// mode's unfolding (Eq. (3)) stored row-major, rows padded to a multiple of
+// 8 columns, one plane per term.  A row of the unfolding is then contiguous,
+// so the A operand of a step (BM rows x 32 columns) arrives as aligned
+// 16-byte loads of 8 consecutive K for one row -- exactly the register
+// layout of the v_mfma_f32_16x16x32_bf16 operands -- and is copied to LDS
+// unchanged.
+//
+// Khatri-Rao generation.  A thread owns one column c of the tile and a run
+// of 8 consecutive K (columns j of the unfolding).  Within the run the
+// lowest other mode's index advances and the higher modes' indices stay
+// fixed unless the run wraps; the product of the higher modes' entries is
+// formed once per run and multiplied by the 8 entries of the lowest mode
+// (the order highest mode first, as in Eq. (1)).  Runs that wrap take a
+// per-entry path.  Each entry is split into its bfloat16 terms with the
+// hardware round-to-nearest-even conversion and 8 terms are written to LDS
+// as one 16-byte store, again in the operand's register layout.
+//
+// Tiles are BM x BN with BM = 16 WM TM covering all rows of small modes, so
+// each Khatri-Rao entry is generated once per column tile; blocks are dealt
+// to the XCDs in contiguous runs of column tiles (they share the tensor
+// slice in L2).  The next step's loads are issued before the matrix-core work
+// of the current step and stored after it (double-buffered LDS, one barrier).
 #include "jkc_internal.hpp"
 
 namespace jkc {
@@ -32,9 +56,10 @@ namespace {
 constexpr int kBK = 32;           // one v_mfma_f32_16x16x32_bf16 deep
 constexpr int kLdk = kBK + 8;     // LDS row pitch in bf16 elements (80 bytes)
 constexpr int kFlushK = 2048;     // float32 accumulation span before a float64 flush
+constexpr int kXcds = 8;
 
-// Incremental walk over columns j of the unfolding (lowest other mode
-// fastest, Eq. (3)); no divisions once initialised.
+// Multi-index of the other modes for column j of the unfolding (lowest
+// other mode fastest, Eq. (3)), advanced incrementally.
 struct Walk {
   uint32_t idx[kMaxOrder - 1];
   int64_t j;
@@ -59,34 +84,25 @@ struct Walk {
       }
     }
   }
-  __device__ int64_t toff(const MttkrpArgs& a) const {
-    return (int64_t)idx[0] * a.ostride[0] + (int64_t)idx[1] * a.ostride[1] +
-           (int64_t)idx[2] * a.ostride[2];
-  }
 };
 
-__device__ inline uint16_t bf16_bits(__bf16 x) { return __builtin_bit_cast(uint16_t, x); }
-
-__device__ inline uint4 pack8(const uint16_t* v) {
-  uint4 r;
-  r.x = v[0] | ((uint32_t)v[1] << 16);
-  r.y = v[2] | ((uint32_t)v[3] << 16);
-  r.z = v[4] | ((uint32_t)v[5] << 16);
-  r.w = v[6] | ((uint32_t)v[7] << 16);
-  return r;
+__device__ inline uint32_t pack2(__bf16 lo, __bf16 hi) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, lo) |
+         ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
 }
 
-template <int WM, int WN, int TM, int TN, int NTERM>
+template <int WM, int WN, int TM, int TN, int NTERM, int NO>
 __global__ void __launch_bounds__(64 * WM * WN)
-k_mttkrp_split(const MttkrpArgs a) {
+k_mttkrp_bf(const MttkrpArgs a) {
   constexpr int NT = 64 * WM * WN;
   constexpr int BM = WM * TM * 16;
   constexpr int BN = WN * TN * 16;
   constexpr int BK = kBK;
-  constexpr int VA = BM * BK / NT;     // A values per thread per step
-  constexpr int VB = BN * BK / NT;     // B values per thread per step
-  static_assert(VA % 8 == 0 && VB % 8 == 0 && VA <= BK && VB <= BK, "vector widths");
+  constexpr int CH = BK / 8;                         // 8-column runs per row per step
+  constexpr int AI = (BM * CH + NT - 1) / NT;        // A runs per thread
+  constexpr int BI = (BN * CH + NT - 1) / NT;        // B runs per thread
   static_assert(NTERM == 2 || NTERM == 3, "terms");
+  static_assert(NO >= 1 && NO <= kMaxOrder - 1, "other modes");
 
   __shared__ __attribute__((aligned(16))) uint16_t As[2][NTERM][BM][kLdk];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][NTERM][BN][kLdk];
@@ -97,108 +113,128 @@ k_mttkrp_split(const MttkrpArgs a) {
   const int wm = wave % WM;
   const int wn = wave / WM;
 
-  const int tile = blockIdx.x;
-  const int split = blockIdx.y;
-  const int mt = tile % a.mtiles;
-  const int nt = tile / a.mtiles;
+  // Block -> (column tile, row tile, K chunk), XCD-aware as in the float64
+  // kernel: each XCD receives a contiguous run of logical blocks, column
+  // tile fastest, so the blocks sharing one tensor slice share an L2.
+  const int total = gridDim.x;
+  int logical = blockIdx.x;
+  const int per_xcd = total / kXcds;
+  if (logical < per_xcd * kXcds) logical = (logical % kXcds) * per_xcd + logical / kXcds;
+  const int nt = logical % a.ntiles;
+  const int mt = (logical / a.ntiles) % a.mtiles;
+  const int split = logical / (a.ntiles * a.mtiles);
   const int i0 = mt * BM;
   const int c0 = nt * BN;
   const int64_t kbeg = (int64_t)split * a.kchunk;
   const int64_t kend = min(kbeg + a.kchunk, a.J);
   const int nsteps = kend > kbeg ? (int)((kend - kbeg + BK - 1) / BK) : 0;
 
-  // A roles.  Unit-stride mode: a thread owns one row and a run of VA
-  // consecutive columns (row-contiguous global loads, 16-byte LDS writes).
-  // Otherwise: a thread owns one column and VA rows (column-contiguous loads).
-  const bool m_fast = a.stride_n == 1;
-  const int aRow = m_fast ? tid % BM : (tid / BK) * VA;
-  const int aK = m_fast ? (tid / BM) * VA : tid % BK;
-  // B roles: a thread owns one Khatri-Rao column and VB consecutive k.
-  const int bCol = tid % BN;
-  const int bK = (tid / BN) * VB;
-
-  Walk wA, wB;
-  wA.init(a, kbeg + aK);
-  wB.init(a, kbeg + bK);
-
   const uint16_t* __restrict__ Tp = static_cast<const uint16_t*>(a.T);
 
-  uint16_t ra[NTERM][VA];
-  float rb[kMaxOrder - 1][VB];   // factor entries, rounded to float32 on load
+  // A runs: item e = tid + NT*u -> row e / CH, run e % CH (CH threads cover
+  // one row's 64 contiguous bytes per term).
+  uint4 ra[AI][NTERM];
+  bool aok[AI];
+  // B runs: item e -> column e % BN (consecutive threads, consecutive
+  // columns: coalesced factor loads), run e / BN.
+  Walk wb[BI];
+#pragma unroll
+  for (int u = 0; u < BI; ++u) wb[u].init(a, kbeg + 8 * ((tid + NT * u) / BN));
+  double rlow[BI][8];        // the lowest other mode's 8 entries
+  double rhigh[BI][NO];      // the higher modes' entries (fast path)
+  bool bfast[BI], bok[BI];
 
-  auto load_step = [&]() {
-    if (m_fast) {
-      Walk w = wA;
-      const int row = i0 + aRow;
+  auto load_step = [&](int s) {
+    const int64_t j0 = kbeg + (int64_t)s * BK;
 #pragma unroll
-      for (int v = 0; v < VA; ++v) {
-        const bool ok = w.j < kend && row < a.M;
-        const int64_t addr = w.toff(a) + row;
+    for (int u = 0; u < AI; ++u) {
+      const int e = tid + NT * u;
+      const int row = e / CH, run = e % CH;
+      const int64_t j = j0 + 8 * run;
+      const bool ok = e < BM * CH && i0 + row < a.M && j < kend;
+      aok[u] = ok;
+      const int64_t at = ok ? (int64_t)(i0 + row) * a.ldt + j : 0;
 #pragma unroll
-        for (int t = 0; t < NTERM; ++t) ra[t][v] = ok ? Tp[t * a.plane + addr] : (uint16_t)0;
-        w.advance(a, 1);
-      }
-    } else {
-      const bool ok = wA.j < kend;
-      const int64_t toff = wA.toff(a);
-#pragma unroll
-      for (int v = 0; v < VA; ++v) {
-        const int row = i0 + aRow + v;
-        const bool okr = ok && row < a.M;
-        const int64_t addr = toff + (int64_t)row * a.stride_n;
-#pragma unroll
-        for (int t = 0; t < NTERM; ++t) ra[t][v] = okr ? Tp[t * a.plane + addr] : (uint16_t)0;
-      }
+      for (int t = 0; t < NTERM; ++t)
+        ra[u][t] = *reinterpret_cast<const uint4*>(Tp + (int64_t)t * a.plane + at);
     }
-    Walk w = wB;
-    const int col = c0 + bCol;
 #pragma unroll
-    for (int v = 0; v < VB; ++v) {
-      const bool ok = w.j < kend && col < a.ncols;
+    for (int u = 0; u < BI; ++u) {
+      const int e = tid + NT * u;
+      const int col = c0 + e % BN;
+      const Walk& w = wb[u];
+      const bool ok = e < BN * CH && col < a.ldc && w.j < kend;
+      bok[u] = ok;
+      // fast path: the run neither wraps the lowest mode nor crosses kend
+      const bool fast = ok && w.idx[0] + 8 <= (uint32_t)a.odim[0] && w.j + 8 <= kend;
+      bfast[u] = fast;
+      const int cc = ok ? col : 0;
+      const uint32_t i_low = fast ? w.idx[0] : 0u;
+      const double* u0 = a.oU[0] + (int64_t)i_low * a.ldc + cc;
 #pragma unroll
-      for (int q = 0; q < kMaxOrder - 1; ++q)
-        if (q < a.nother) rb[q][v] = ok ? (float)a.oU[q][(int64_t)w.idx[q] * a.ldc + col] : 0.f;
-      w.advance(a, 1);
+      for (int v = 0; v < 8; ++v) rlow[u][v] = u0[(int64_t)v * (fast ? a.ldc : 0)];
+#pragma unroll
+      for (int q = 1; q < NO; ++q) rhigh[u][q] = a.oU[q][(int64_t)(ok ? w.idx[q] : 0u) * a.ldc + cc];
     }
   };
+
   auto store_step = [&](int buf) {
 #pragma unroll
-    for (int t = 0; t < NTERM; ++t) {
-      if (m_fast) {
+    for (int u = 0; u < AI; ++u) {
+      const int e = tid + NT * u;
+      if (e < BM * CH) {
+        const int row = e / CH, run = e % CH;
 #pragma unroll
-        for (int v = 0; v < VA; v += 8)
-          *reinterpret_cast<uint4*>(&As[buf][t][aRow][aK + v]) = pack8(&ra[t][v]);
-      } else {
-#pragma unroll
-        for (int v = 0; v < VA; ++v) As[buf][t][aRow + v][aK] = ra[t][v];
+        for (int t = 0; t < NTERM; ++t)
+          *reinterpret_cast<uint4*>(&As[buf][t][row][8 * run]) =
+              aok[u] ? ra[u][t] : make_uint4(0, 0, 0, 0);
       }
     }
-    uint16_t bt[NTERM][VB];
 #pragma unroll
-    for (int v = 0; v < VB; ++v) {
-      // Khatri-Rao entry in float32 (highest mode first, Eq. (1) order),
-      // split into bfloat16 terms with the hardware round-to-nearest-even
-      // conversion; each remainder is exact in float32.
-      float f = 0.f;
-      bool first = true;
+    for (int u = 0; u < BI; ++u) {
+      const int e = tid + NT * u;
+      if (e >= BN * CH) continue;
+      const int cl = e % BN, run = e / BN;
+      float f[8];
+      if (bfast[u]) {
+        float hi = 1.f;
 #pragma unroll
-      for (int q = kMaxOrder - 2; q >= 0; --q)
-        if (q < a.nother) {
-          f = first ? rb[q][v] : f * rb[q][v];
-          first = false;
+        for (int q = NO - 1; q >= 1; --q) hi = (q == NO - 1) ? (float)rhigh[u][q] : hi * (float)rhigh[u][q];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) f[v] = NO == 1 ? (float)rlow[u][v] : hi * (float)rlow[u][v];
+      } else {
+        // runs that wrap, end the chunk or lie outside the tile: entry by entry
+        Walk w = wb[u];
+        const int col = c0 + cl;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          float x = 0.f;
+          if (bok[u] && w.j < kend) {
+#pragma unroll
+            for (int q = NO - 1; q >= 0; --q) {
+              const float y = (float)a.oU[q][(int64_t)w.idx[q] * a.ldc + col];
+              x = (q == NO - 1) ? y : x * y;
+            }
+          }
+          f[v] = x;
+          w.advance(a, 1);
         }
+      }
 #pragma unroll
       for (int t = 0; t < NTERM; ++t) {
-        const __bf16 h = (__bf16)f;
-        bt[t][v] = bf16_bits(h);
-        f = f - (float)h;
+        uint32_t wds[4];
+#pragma unroll
+        for (int v = 0; v < 8; v += 2) {
+          const __bf16 h0 = (__bf16)f[v];
+          const __bf16 h1 = (__bf16)f[v + 1];
+          wds[v / 2] = pack2(h0, h1);
+          f[v] -= (float)h0;
+          f[v + 1] -= (float)h1;
+        }
+        *reinterpret_cast<uint4*>(&Bs[buf][t][cl][8 * run]) =
+            make_uint4(wds[0], wds[1], wds[2], wds[3]);
       }
     }
-#pragma unroll
-    for (int t = 0; t < NTERM; ++t)
-#pragma unroll
-      for (int v = 0; v < VB; v += 8)
-        *reinterpret_cast<uint4*>(&Bs[buf][t][bCol][bK + v]) = pack8(&bt[t][v]);
   };
 
   v4f accf[TM][TN];
@@ -212,7 +248,7 @@ k_mttkrp_split(const MttkrpArgs a) {
     }
 
   if (nsteps > 0) {
-    load_step();
+    load_step(0);
     store_step(0);
   }
   __syncthreads();
@@ -225,35 +261,36 @@ k_mttkrp_split(const MttkrpArgs a) {
     const int buf = s & 1;
     const bool more = s + 1 < nsteps;
     if (more) {
-      wA.advance(a, BK);
-      wB.advance(a, BK);
-      load_step();
+#pragma unroll
+      for (int u = 0; u < BI; ++u) wb[u].advance(a, BK);
+      load_step(s + 1);
     }
-    bf16x8 af[NTERM][TM], bfr[NTERM][TN];
+    bf16x8 bfr[NTERM][TN];
 #pragma unroll
-    for (int t = 0; t < NTERM; ++t) {
-#pragma unroll
-      for (int x = 0; x < TM; ++x)
-        af[t][x] = *reinterpret_cast<const bf16x8*>(&As[buf][t][arow + x * 16][kq]);
+    for (int t = 0; t < NTERM; ++t)
 #pragma unroll
       for (int y = 0; y < TN; ++y)
         bfr[t][y] = *reinterpret_cast<const bf16x8*>(&Bs[buf][t][bcol + y * 16][kq]);
-    }
 #pragma unroll
-    for (int x = 0; x < TM; ++x)
+    for (int x = 0; x < TM; ++x) {
+      bf16x8 af[NTERM];
+#pragma unroll
+      for (int t = 0; t < NTERM; ++t)
+        af[t] = *reinterpret_cast<const bf16x8*>(&As[buf][t][arow + x * 16][kq]);
 #pragma unroll
       for (int y = 0; y < TN; ++y) {
         v4f c = accf[x][y];
         if constexpr (NTERM == 3) {
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2][x], bfr[0][y], c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][x], bfr[1][y], c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][x], bfr[2][y], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2], bfr[0][y], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1], bfr[1][y], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bfr[2][y], c, 0, 0, 0);
         }
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][x], bfr[0][y], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][x], bfr[1][y], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][x], bfr[0][y], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1], bfr[0][y], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bfr[1][y], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bfr[0][y], c, 0, 0, 0);
         accf[x][y] = c;
       }
+    }
     since_flush += BK;
     if (since_flush >= kFlushK) {
 #pragma unroll
@@ -288,29 +325,44 @@ k_mttkrp_split(const MttkrpArgs a) {
 }
 
 template <int WM, int WN, int TM, int TN, int NTERM>
-hipError_t launch_split(const MttkrpArgs& a, hipStream_t s) {
-  dim3 grid(a.mtiles * a.ntiles, a.splits);
-  hipLaunchKernelGGL((k_mttkrp_split<WM, WN, TM, TN, NTERM>), grid, dim3(64 * WM * WN), 0, s, a);
+hipError_t launch_bf(const MttkrpArgs& a, hipStream_t s) {
+  const dim3 grid(a.mtiles * a.ntiles * a.splits);
+  const dim3 block(64 * WM * WN);
+  switch (a.nother) {
+    case 1: hipLaunchKernelGGL((k_mttkrp_bf<WM, WN, TM, TN, NTERM, 1>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_mttkrp_bf<WM, WN, TM, TN, NTERM, 2>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_mttkrp_bf<WM, WN, TM, TN, NTERM, 3>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 }  // namespace
 
+// instr = 0: tiles of 16-row matrix-core blocks (the host derives the row
+// tile as wm * tm * 16 from it); the term count is fixed by the table.
+#define JKC_BF_VARIANT(WM, WN, TM, TN, NTERM) \
+  { WM, WN, TM, TN, kBK, &launch_bf<WM, WN, TM, TN, NTERM>, 0 }
+
 const std::vector<MttkrpVariant>& mttkrp_split_variants() {
   static const std::vector<MttkrpVariant> v = {
-      {2, 2, 2, 2, kBK, &launch_split<2, 2, 2, 2, 2>, 2},   // 64 x 64
-      {2, 2, 4, 2, kBK, &launch_split<2, 2, 4, 2, 2>, 2},   // 128 x 64
-      {2, 2, 2, 4, kBK, &launch_split<2, 2, 2, 4, 2>, 2},   // 64 x 128
-      {2, 2, 4, 4, kBK, &launch_split<2, 2, 4, 4, 2>, 2},   // 128 x 128
+      JKC_BF_VARIANT(2, 2, 7, 2, 2),   // 224 x 64
+      JKC_BF_VARIANT(2, 2, 4, 2, 2),   // 128 x 64
+      JKC_BF_VARIANT(2, 2, 4, 4, 2),   // 128 x 128
+      JKC_BF_VARIANT(1, 4, 7, 2, 2),   // 112 x 128
+      JKC_BF_VARIANT(1, 4, 5, 2, 2),   // 80 x 128
+      JKC_BF_VARIANT(2, 2, 2, 2, 2),   // 64 x 64
   };
   return v;
 }
 
 const std::vector<MttkrpVariant>& mttkrp_split3_variants() {
   static const std::vector<MttkrpVariant> v = {
-      {2, 2, 2, 2, kBK, &launch_split<2, 2, 2, 2, 3>, 3},   // 64 x 64
-      {2, 2, 4, 2, kBK, &launch_split<2, 2, 4, 2, 3>, 3},   // 128 x 64
-      {2, 2, 2, 4, kBK, &launch_split<2, 2, 2, 4, 3>, 3},   // 64 x 128
+      JKC_BF_VARIANT(2, 2, 7, 2, 3),   // 224 x 64
+      JKC_BF_VARIANT(2, 2, 4, 2, 3),   // 128 x 64
+      JKC_BF_VARIANT(1, 4, 7, 2, 3),   // 112 x 128
+      JKC_BF_VARIANT(1, 4, 5, 2, 3),   // 80 x 128
+      JKC_BF_VARIANT(2, 2, 2, 2, 3),   // 64 x 64
   };
   return v;
 }

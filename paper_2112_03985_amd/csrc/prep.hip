@@ -61,15 +61,39 @@ __device__ inline double bf16_to_double(uint16_t h) {
 
 // x = t_1 + t_2 + ... : t_1 = bf16(x), t_2 = bf16(x - t_1), ... (each
 // remainder exact in float64), plane t at planes + t * n.
-__global__ void k_split_tensor(const void* src, int32_t src_f32, uint16_t* planes,
-                               int32_t nterm, int64_t n) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+// One thread per element (i, j) of the mode-n unfolding, row-major with
+// pitch ldt; column j maps to the other modes' indices lowest-first (Eq.
+// (3)).  Padding columns j >= J are zero.
+__global__ void k_split_unfold(const void* src, int32_t src_f32, int32_t N, int64_t d0,
+                               int64_t d1, int64_t d2, int64_t d3, int32_t n, int64_t ldt,
+                               int32_t nterm, uint16_t* planes) {
+  const int64_t dims[4] = {d0, d1, d2, d3};
+  int64_t stride[4];
+  int64_t P = 1;
+  for (int m = 0; m < 4; ++m) {
+    stride[m] = P;
+    if (m < N) P *= dims[m];
+  }
+  const int64_t I = dims[n];
+  const int64_t J = P / I;
+  const int64_t total = I * ldt;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    double x = src_f32 ? (double)static_cast<const float*>(src)[e]
-                       : static_cast<const double*>(src)[e];
+    const int64_t i = e / ldt;
+    const int64_t j = e - i * ldt;
+    double x = 0.0;
+    if (j < J) {
+      int64_t rem = j, off = i * stride[n];
+      for (int m = 0; m < N; ++m) {
+        if (m == n) continue;
+        off += (rem % dims[m]) * stride[m];
+        rem /= dims[m];
+      }
+      x = src_f32 ? (double)static_cast<const float*>(src)[off] : static_cast<const double*>(src)[off];
+    }
     for (int t = 0; t < nterm; ++t) {
       const uint16_t h = bf16_rne(x);
-      planes[(int64_t)t * n + e] = h;
+      planes[(int64_t)t * total + e] = h;
       x -= bf16_to_double(h);
     }
   }
@@ -209,10 +233,13 @@ hipError_t launch_copy_tensor(const void* src, int32_t src_f32, void* dst, int64
   return hipGetLastError();
 }
 
-hipError_t launch_split_tensor(const void* src, int32_t src_f32, uint16_t* planes,
-                               int32_t nterm, int64_t count, hipStream_t s) {
-  hipLaunchKernelGGL(k_split_tensor, dim3(grid_for(count)), dim3(256), 0, s, src, src_f32,
-                     planes, nterm, count);
+hipError_t launch_split_unfold(const void* src, int32_t src_f32, int32_t N, const int64_t* dims,
+                               int32_t n, int64_t ldt, int32_t nterm, uint16_t* planes,
+                               hipStream_t s) {
+  const int64_t total = dims[n] * ldt;
+  hipLaunchKernelGGL(k_split_unfold, dim3(grid_for(total)), dim3(256), 0, s, src, src_f32, N,
+                     dims[0], N > 1 ? dims[1] : 1, N > 2 ? dims[2] : 1, N > 3 ? dims[3] : 1, n,
+                     ldt, nterm, planes);
   return hipGetLastError();
 }
 
