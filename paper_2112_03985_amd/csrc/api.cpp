@@ -108,6 +108,8 @@ struct Plan {
     items.push_back({"slice", dims[nhat] * 8});
     items.push_back({"slice_part", (int64_t)kSliceChunks * dims[nhat] * 8});
     items.push_back({"counter", 4});
+    // split paths: float32 copies of the factors, refreshed before each MTTKRP
+    for (int n = 0; n < N; ++n) items.push_back({"Uf", precision != JKC_FP64 ? dims[n] * ldc * 4 : 0});
     total = 0;
     for (auto& it : items) total += align_up(std::max<int64_t>(it.bytes, 1), kAlign);
   }
@@ -178,6 +180,11 @@ jkc_status make_plan(const jkc_problem* prob, Plan* pl) {
   pl->copy_tensor = prob->copy_tensor;
   if (!pl->copy_tensor && pl->precision != JKC_FP64)
     return fail(JKC_EINVAL, "copy_tensor = 0 needs precision JKC_FP64");
+  if (pl->precision != JKC_FP64)
+    for (int n = 0; n < pl->N; ++n)
+      if (pl->dims[n] * align_up(P / pl->dims[n], 8) >= (1ll << 31) ||
+          pl->dims[n] * (int64_t)pl->ldc >= (1ll << 31))
+        return fail(JKC_EINVAL, "split precision needs every unfolding and factor below 2^31 elements");
   pl->maxI = 0;
   pl->partial_doubles = 0;
   for (int n = 0; n < pl->N; ++n) {
@@ -373,6 +380,11 @@ jkc_status enqueue_mttkrp(jkc_ctx* ctx, int n, const Tiling& t) {
     a.T = ctx->T_planes + ctx->tp_off[n];
     a.plane = ctx->dims[n] * ctx->tp_ld[n];
     a.ldt = ctx->tp_ld[n];
+    for (int m = 0, q = 0; m < ctx->N; ++m) {
+      if (m == n) continue;
+      JKC_HIP(launch_to_f32(ctx->U[m], ctx->dims[m] * ctx->ldc, ctx->Uf[m], ctx->stream));
+      a.oUf[q++] = ctx->Uf[m];
+    }
   } else {
     a.T = ctx->T;
     a.plane = 0;
@@ -724,6 +736,7 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
   c.slice = static_cast<double*>(take(it++));
   c.slice_part = static_cast<double*>(take(it++));
   c.counter = static_cast<int32_t*>(take(it++));
+  for (int n = 0; n < pl.N; ++n) c.Uf[n] = static_cast<float*>(take(it++));
 
   hipStream_t st = c.stream;
   // model tables (host vectors live in the context, so the copies are safe)

@@ -50,6 +50,7 @@ struct MttkrpArgs {
   int64_t J;                // columns of the unfolding
   int64_t kchunk;           // K elements per split (multiple of BK)
   int64_t ldt;              // split paths: row pitch of the unfolded planes
+  const float* oUf[kMaxOrder - 1];   // split paths: float32 copies of oU
   int32_t ldc;              // leading dimension of factors and partials
   int32_t ncols;            // columns to produce (<= ldc)
   int32_t mtiles, ntiles;
@@ -128,6 +129,7 @@ hipError_t launch_copy_tensor(const void* src, int32_t src_f32, void* dst,
 // Split-precision tensor copy of one mode: the mode-n unfolding (Eq. (3))
 // stored row-major with row pitch ldt (>= P / I_n, a multiple of 8, padding
 // zero), as nterm bfloat16 planes of I_n * ldt elements.
+hipError_t launch_to_f32(const double* src, int64_t n, float* dst, hipStream_t s);
 hipError_t launch_split_unfold(const void* src, int32_t src_f32, int32_t N, const int64_t* dims,
                                int32_t n, int64_t ldt, int32_t nterm, uint16_t* planes,
                                hipStream_t s);
@@ -199,6 +201,7 @@ struct jkc_ctx {
   int64_t tp_off[jkc::kMaxOrder] = {0, 0, 0, 0};   // element offset of mode n's planes
   int64_t tp_ld[jkc::kMaxOrder] = {0, 0, 0, 0};    // their row pitch
   double* U[jkc::kMaxOrder] = {nullptr, nullptr, nullptr, nullptr};
+  float* Uf[jkc::kMaxOrder] = {nullptr, nullptr, nullptr, nullptr};   // split paths
   double* G[jkc::kMaxOrder] = {nullptr, nullptr, nullptr, nullptr};
   double* Mbuf = nullptr;        // [max I_n][ldc]
   double* partial = nullptr;     // split-K partials

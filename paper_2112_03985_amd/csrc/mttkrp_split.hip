@@ -6,7 +6,8 @@
 // round-to-nearest-even of what the previous terms leave (x1 = bf16(x),
 // x2 = bf16(x - x1), ...): the tensor once at init, directly from float64;
 // the Khatri-Rao entries as they are generated, from a float32 product of the
-// factor entries.  Products keep every term pair whose magnitude is at least
+// factor entries (read from float32 copies of the factors made before each
+// launch).  Products keep every term pair whose magnitude is at least
 // 2^-8(NTERM-1) of the leading one:
 //   NTERM = 2: a1 b1 + a1 b2 + a2 b1                       (3 MFMA products)
 //   NTERM = 3: the above + a1 b3 + a2 b2 + a3 b1           (6 MFMA products)
@@ -86,10 +87,6 @@ struct Walk {
   }
 };
 
-__device__ inline uint32_t pack2(__bf16 lo, __bf16 hi) {
-  return (uint32_t)__builtin_bit_cast(uint16_t, lo) |
-         ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
-}
 
 template <int WM, int WN, int TM, int TN, int NTERM, int NO>
 __global__ void __launch_bounds__(64 * WM * WN)
@@ -132,17 +129,24 @@ k_mttkrp_bf(const MttkrpArgs a) {
   const uint16_t* __restrict__ Tp = static_cast<const uint16_t*>(a.T);
 
   // A runs: item e = tid + NT*u -> row e / CH, run e % CH (CH threads cover
-  // one row's 64 contiguous bytes per term).
+  // one row's 64 contiguous bytes per term).  Runs outside the tile or past
+  // the chunk read a clamped address and are not masked: past the chunk they
+  // meet zero Khatri-Rao entries, and rows past I_n produce output rows that
+  // are never stored (a non-finite tensor entry therefore only affects its
+  // own output row, which is non-finite in the exact product too).
   uint4 ra[AI][NTERM];
-  bool aok[AI];
+  const uint16_t* __restrict__ Tt[NTERM];
+#pragma unroll
+  for (int t = 0; t < NTERM; ++t) Tt[t] = Tp + (int64_t)t * a.plane;
   // B runs: item e -> column e % BN (consecutive threads, consecutive
   // columns: coalesced factor loads), run e / BN.
   Walk wb[BI];
 #pragma unroll
   for (int u = 0; u < BI; ++u) wb[u].init(a, kbeg + 8 * ((tid + NT * u) / BN));
-  double rlow[BI][8];        // the lowest other mode's 8 entries
-  double rhigh[BI][NO];      // the higher modes' entries (fast path)
+  float rlow[BI][8];         // the lowest other mode's 8 entries
+  float rhigh[BI][NO];       // the higher modes' entries (fast path)
   bool bfast[BI], bok[BI];
+  const uint32_t ldc = (uint32_t)a.ldc;
 
   auto load_step = [&](int s) {
     const int64_t j0 = kbeg + (int64_t)s * BK;
@@ -152,11 +156,10 @@ k_mttkrp_bf(const MttkrpArgs a) {
       const int row = e / CH, run = e % CH;
       const int64_t j = j0 + 8 * run;
       const bool ok = e < BM * CH && i0 + row < a.M && j < kend;
-      aok[u] = ok;
-      const int64_t at = ok ? (int64_t)(i0 + row) * a.ldt + j : 0;
+      // element offset within a plane: below 2^31 (checked at init)
+      const uint32_t at = ok ? (uint32_t)(i0 + row) * (uint32_t)a.ldt + (uint32_t)j : 0u;
 #pragma unroll
-      for (int t = 0; t < NTERM; ++t)
-        ra[u][t] = *reinterpret_cast<const uint4*>(Tp + (int64_t)t * a.plane + at);
+      for (int t = 0; t < NTERM; ++t) ra[u][t] = *reinterpret_cast<const uint4*>(Tt[t] + at);
     }
 #pragma unroll
     for (int u = 0; u < BI; ++u) {
@@ -168,13 +171,19 @@ k_mttkrp_bf(const MttkrpArgs a) {
       // fast path: the run neither wraps the lowest mode nor crosses kend
       const bool fast = ok && w.idx[0] + 8 <= (uint32_t)a.odim[0] && w.j + 8 <= kend;
       bfast[u] = fast;
-      const int cc = ok ? col : 0;
-      const uint32_t i_low = fast ? w.idx[0] : 0u;
-      const double* u0 = a.oU[0] + (int64_t)i_low * a.ldc + cc;
+      // float32 factor copies, 32-bit element offsets (below 2^31, checked
+      // at init); rows i_low .. i_low+7 exist on the fast path, row 0 is read
+      // eight times otherwise
+      const uint32_t cc = ok ? (uint32_t)col : 0u;
+      const uint32_t step = fast ? ldc : 0u;
+      uint32_t o0 = (fast ? w.idx[0] : 0u) * ldc + cc;
 #pragma unroll
-      for (int v = 0; v < 8; ++v) rlow[u][v] = u0[(int64_t)v * (fast ? a.ldc : 0)];
+      for (int v = 0; v < 8; ++v) {
+        rlow[u][v] = a.oUf[0][o0];
+        o0 += step;
+      }
 #pragma unroll
-      for (int q = 1; q < NO; ++q) rhigh[u][q] = a.oU[q][(int64_t)(ok ? w.idx[q] : 0u) * a.ldc + cc];
+      for (int q = 1; q < NO; ++q) rhigh[u][q] = a.oUf[q][(ok ? w.idx[q] : 0u) * ldc + cc];
     }
   };
 
@@ -185,9 +194,7 @@ k_mttkrp_bf(const MttkrpArgs a) {
       if (e < BM * CH) {
         const int row = e / CH, run = e % CH;
 #pragma unroll
-        for (int t = 0; t < NTERM; ++t)
-          *reinterpret_cast<uint4*>(&As[buf][t][row][8 * run]) =
-              aok[u] ? ra[u][t] : make_uint4(0, 0, 0, 0);
+        for (int t = 0; t < NTERM; ++t) *reinterpret_cast<uint4*>(&As[buf][t][row][8 * run]) = ra[u][t];
       }
     }
 #pragma unroll
@@ -199,9 +206,9 @@ k_mttkrp_bf(const MttkrpArgs a) {
       if (bfast[u]) {
         float hi = 1.f;
 #pragma unroll
-        for (int q = NO - 1; q >= 1; --q) hi = (q == NO - 1) ? (float)rhigh[u][q] : hi * (float)rhigh[u][q];
+        for (int q = NO - 1; q >= 1; --q) hi = (q == NO - 1) ? rhigh[u][q] : hi * rhigh[u][q];
 #pragma unroll
-        for (int v = 0; v < 8; ++v) f[v] = NO == 1 ? (float)rlow[u][v] : hi * (float)rlow[u][v];
+        for (int v = 0; v < 8; ++v) f[v] = NO == 1 ? rlow[u][v] : hi * rlow[u][v];
       } else {
         // runs that wrap, end the chunk or lie outside the tile: entry by entry
         Walk w = wb[u];
@@ -212,7 +219,7 @@ k_mttkrp_bf(const MttkrpArgs a) {
           if (bok[u] && w.j < kend) {
 #pragma unroll
             for (int q = NO - 1; q >= 0; --q) {
-              const float y = (float)a.oU[q][(int64_t)w.idx[q] * a.ldc + col];
+              const float y = a.oUf[q][w.idx[q] * ldc + (uint32_t)col];
               x = (q == NO - 1) ? y : x * y;
             }
           }
@@ -225,9 +232,12 @@ k_mttkrp_bf(const MttkrpArgs a) {
         uint32_t wds[4];
 #pragma unroll
         for (int v = 0; v < 8; v += 2) {
+          // round-to-nearest-even conversion of two entries; the remainders
+          // are exact in float32
           const __bf16 h0 = (__bf16)f[v];
           const __bf16 h1 = (__bf16)f[v + 1];
-          wds[v / 2] = pack2(h0, h1);
+          wds[v / 2] = (uint32_t)__builtin_bit_cast(uint16_t, h0) |
+                       ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
           f[v] -= (float)h0;
           f[v + 1] -= (float)h1;
         }

@@ -233,6 +233,17 @@ hipError_t launch_copy_tensor(const void* src, int32_t src_f32, void* dst, int64
   return hipGetLastError();
 }
 
+__global__ void k_to_f32(const double* src, int64_t n, float* dst) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = (float)src[e];
+}
+
+hipError_t launch_to_f32(const double* src, int64_t n, float* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(256), 0, s, src, n, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_split_unfold(const void* src, int32_t src_f32, int32_t N, const int64_t* dims,
                                int32_t n, int64_t ldt, int32_t nterm, uint16_t* planes,
                                hipStream_t s) {
