@@ -383,6 +383,15 @@ __global__ void __launch_bounds__(kThreads) k_update_lds(const UpdateArgs a) {
     const int p = a.mt.left[k];
     const int64_t goff = a.mt.goff[k];
     const int zero_row = (a.n == a.nhat) ? p : -1;
+    // per-model scalars of the error step, fetched now so that their latency
+    // overlaps the update
+    double pre_nt2 = 0.0, pre_fprev = 0.0;
+    int32_t pre_it = 0;
+    if (t == 0 && a.last_mode) {
+      pre_nt2 = a.normT2[k];
+      pre_fprev = a.fit_prev[k];
+      pre_it = a.iters[k];
+    }
 
     // H and the reduced block of M, loads issued together
     for (int e = t; e < R * R; e += blockDim.x) {
@@ -592,14 +601,14 @@ __global__ void __launch_bounds__(kThreads) k_update_lds(const UpdateArgs a) {
         double quad = 0.0;
         for (int r = 0; r < R; ++r)
           for (int c = 0; c < R; ++c) quad += lam[r] * H[r * ld + c] * Gs[r * ld + c] * lam[c];
-        const double nt2 = a.normT2[k];
+        const double nt2 = pre_nt2;
         const double e = nt2 + quad - 2.0 * in;
         const double f = 1.0 - sqrt(fmax(e, 0.0)) / sqrt(nt2);
-        const int it = a.iters[k] + 1;
+        const int it = pre_it + 1;
         a.iters[k] = it;
         a.err[k] = e;
         if (!isfinite(e)) nst |= JKC_ST_NONFINITE;
-        if (a.check_conv && a.tol > 0.0 && it >= 2 && fabs(f - a.fit_prev[k]) < a.tol)
+        if (a.check_conv && a.tol > 0.0 && it >= 2 && fabs(f - pre_fprev) < a.tol)
           nst |= JKC_ST_CONVERGED;
         a.fit_prev[k] = f;
         a.fit[k] = f;

@@ -66,6 +66,7 @@ def test_workspace_size_valid_problem():
     (dict(tensor_dtype=5), "tensor_dtype"),
     (dict(precision=1, copy_tensor=0), "copy_tensor"),
     (dict(copy_tensor=3), "copy_tensor"),
+    (dict(dims=[2 ** 15, 2 ** 15, 4], precision=1), "split precision needs"),
 ])
 def test_invalid_problems_rejected(kw, msg):
     with pytest.raises(jk.JkcError) as e:
@@ -110,6 +111,10 @@ def test_null_context_rejected(L):
     assert L.jk_cals_refine(None, 1, None) == jk.JKC_EINVAL
     assert L.jk_cals_tune(None, 1) == jk.JKC_EINVAL
     assert L.jk_cals_set_tiling(None, 0, 0, 1) == jk.JKC_EINVAL
+    assert L.jk_cals_set_update_kernel(None, 0) == jk.JKC_EINVAL
+    assert L.jk_cals_set_sweep_graph(None, 1) == jk.JKC_EINVAL
+    assert L.jk_cals_profile(None, 1) == jk.JKC_EINVAL
+    assert L.jk_cals_profile_read(None, None, None) == jk.JKC_EINVAL
     assert L.jk_cals_num_tilings(None) == 0
     assert L.jk_cals_describe(None, 0) == b""
     L.jk_cals_destroy(None)
