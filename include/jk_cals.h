@@ -187,10 +187,17 @@ jkc_status jk_cals_tune(jkc_ctx *ctx, int32_t reps);
 /* The current tiling of `mode` as text, e.g. "f64 wm2 wn2 tm2 tn2 bk16 s8". */
 const char *jk_cals_describe(jkc_ctx *ctx, int32_t mode);
 
-/* Choose the per-model update kernel: 0 = the model's rows staged in LDS,
- * with the split-K MTTKRP reduction fused in, whenever they fit (default);
- * 1 = a separate reduction kernel, then the update working in global
- * memory.  Both compute the same sums in the same order.  Host only. */
+/* Choose the per-model update (Alg. 3 update step): 0 = one block per
+ * model with its rows staged in LDS, the split-K reduction fused in when
+ * there are at most two partials (default; falls back to 1 when the rows
+ * do not fit LDS); 1 = a separate reduction kernel, then one block per model
+ * working in global memory; 2 = row-parallel: one kernel per (model, 64-row
+ * chunk) sums the split-K partials, solves and stages the chunk's rows, a
+ * second normalises them and writes lambda, the Gram block and the error
+ * (more blocks, but slower on the benchmark shape).  All three compute the same
+ * update; sums run in fixed orders (bitwise repeatable per choice), which
+ * differ between choices only by rounding.  EINVAL for other values.
+ * Host only. */
 jkc_status jk_cals_set_update_kernel(jkc_ctx *ctx, int32_t which);
 
 /* Replay multi-sweep runs of jk_cals_sweep from a HIP graph of one sweep,

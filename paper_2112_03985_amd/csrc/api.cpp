@@ -108,6 +108,7 @@ struct Plan {
     items.push_back({"slice", dims[nhat] * 8});
     items.push_back({"slice_part", (int64_t)kSliceChunks * dims[nhat] * 8});
     items.push_back({"counter", 4});
+    items.push_back({"upart", update_rows_scratch(maxI, gsize, K) * 8});
     // split paths: float32 copies of the factors, refreshed before each MTTKRP
     for (int n = 0; n < N; ++n) items.push_back({"Uf", precision != JKC_FP64 ? dims[n] * ldc * 4 : 0});
     total = 0;
@@ -471,10 +472,20 @@ jkc_status enqueue_update(jkc_ctx* ctx, int n, double tol, int check_conv) {
   constexpr int64_t kLdsBudget = 64 * 1024;
   constexpr int kFuseMaxSplits = 2;
   const int64_t lds = update_lds_doubles(ctx->rmax, (int)ctx->dims[n]);
-  const bool staged = ctx->lds_update && lds * 8 <= kLdsBudget;
+  const bool staged = ctx->update_kernel == 0 && lds * 8 <= kLdsBudget;
   const int splits = effective_splits(ctx, n, ctx->tiling[n]);
   UpdateArgs a{};
-  if (staged && splits <= kFuseMaxSplits) {
+  if (ctx->update_kernel == 2) {
+    // row-parallel: the solve kernel sums the split-K partials itself
+    JKC_TRY(enqueue_mttkrp(ctx, n, ctx->tiling[n]));
+    a.partial = splits > 1 ? ctx->partial : ctx->Mbuf;
+    a.splits = splits;
+    a.scratch = ctx->upart;
+    // staging for the unnormalised rows: Mbuf (when it holds the MTTKRP
+    // itself, each element is read and then overwritten by the same block)
+    a.Utmp = ctx->Mbuf;
+    a.nch = (int32_t)((ctx->maxI + kUpdRows - 1) / kUpdRows);
+  } else if (staged && splits <= kFuseMaxSplits) {
     // few partials: the update sums them itself while staging M in LDS
     JKC_TRY(enqueue_mttkrp(ctx, n, ctx->tiling[n]));
     a.partial = splits > 1 ? ctx->partial : ctx->Mbuf;
@@ -512,7 +523,10 @@ jkc_status enqueue_update(jkc_ctx* ctx, int n, double tol, int check_conv) {
   a.tol = tol;
   a.check_conv = check_conv;
   a.rmax = ctx->rmax;
-  JKC_HIP(launch_update(a, ctx->stream));
+  if (ctx->update_kernel == 2)
+    JKC_HIP(launch_update_rows(a, ctx->stream));
+  else
+    JKC_HIP(launch_update(a, ctx->stream));
   return JKC_OK;
 }
 
@@ -736,6 +750,7 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
   c.slice = static_cast<double*>(take(it++));
   c.slice_part = static_cast<double*>(take(it++));
   c.counter = static_cast<int32_t*>(take(it++));
+  c.upart = static_cast<double*>(take(it++));
   for (int n = 0; n < pl.N; ++n) c.Uf[n] = static_cast<float*>(take(it++));
 
   hipStream_t st = c.stream;
@@ -996,8 +1011,8 @@ const char* jk_cals_describe(jkc_ctx* ctx, int32_t mode) {
 
 jkc_status jk_cals_set_update_kernel(jkc_ctx* ctx, int32_t which) {
   JKC_TRY(check_ctx(ctx));
-  if (which != 0 && which != 1) return fail(JKC_EINVAL, "which must be 0 or 1");
-  ctx->lds_update = which == 0;
+  if (which < 0 || which > 2) return fail(JKC_EINVAL, "which must be 0, 1 or 2");
+  ctx->update_kernel = which;
   drop_graph(ctx);
   g_last_error.clear();
   return JKC_OK;

@@ -103,7 +103,17 @@ struct UpdateArgs {
   int32_t check_conv;             // 1: update convergence flags
   int32_t rmax;                   // largest rank (LDS sizing)
   int64_t lds_doubles;            // > 0: LDS-staged kernel with this much dynamic LDS
+  double* scratch;                // row-parallel update: per (model, chunk) sums
+  double* Utmp;                   // row-parallel update: [In][ldc] unnormalised U
+  int32_t nch;                    // row-parallel update: chunks per model
 };
+
+// Rows per block of the row-parallel update, and its scratch (doubles).
+constexpr int kUpdRows = 64;
+inline int64_t update_rows_scratch(int64_t maxI, int64_t gsize, int64_t K) {
+  return ((maxI + kUpdRows - 1) / kUpdRows) * (gsize + 2 * K);
+}
+hipError_t launch_update_rows(const UpdateArgs& a, hipStream_t s);
 
 // Dynamic LDS (doubles) of the LDS-staged update for a mode with `rows` rows.
 int64_t update_lds_doubles(int rmax, int rows);
@@ -230,7 +240,8 @@ struct jkc_ctx {
   int split_max[jkc::kMaxOrder] = {1, 1, 1, 1};
   std::string describe[jkc::kMaxOrder];
   bool lambda_is_one = true;     // lambda folded into the last factor
-  bool lds_update = true;        // LDS-staged fused update when it fits
+  int update_kernel = 0;         // 0 LDS-staged, 1 global, 2 row-parallel
+  double* upart = nullptr;       // row-parallel update scratch
   bool use_graph = true;         // replay sweeps from a captured HIP graph
   hipGraphExec_t graph_exec = nullptr;
 

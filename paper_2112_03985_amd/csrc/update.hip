@@ -627,6 +627,209 @@ __global__ void __launch_bounds__(kThreads) k_gram(const GramArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Row-parallel update (default).  The model's update (Alg. 1 inner step for
+// each submodel of Alg. 3) is split over blocks of kUpdRows rows:
+//   k_solve_rows:    per (model, row chunk): H and H^{-1} (recomputed per
+//                    chunk, R <= 32), the chunk's rows of M summed from the
+//                    split-K partials in ascending split order (row p zero for
+//                    Case I), U = M H^{-1} (unnormalised) written to a staging
+//                    buffer, and the chunk's U^T U (upper triangle) and
+//                    sum U .* M stored;
+//   k_finalize_rows: per (model, row chunk): the chunk sums added in chunk
+//                    order give lambda_r = sqrt((U^T U)_rr); the chunk's rows
+//                    are written normalised to the factor; chunk 0 writes
+//                    lambda, the Gram of the normalised block and, on the last
+//                    mode, the error and fit.
+// Scratch per (model k, chunk c): R^2 + 2 doubles at nch * (goff_k + 2k) +
+// c * (R^2 + 2); slot R^2 holds sum U .* M, slot R^2 + 1 the solve flag
+// (1 Cholesky, 0 pseudoinverse, -1 model frozen), so the finalize kernel
+// never reads the status it may rewrite.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_solve_rows(const UpdateArgs a) {
+  __shared__ double H[kMaxRank][kLd], L[kMaxRank][kLd], Wj[kMaxRank][kLd], Vj[kMaxRank][kLd];
+  __shared__ double Hp[kMaxRank][kLd];
+  __shared__ double Ms[kUpdRows][kLd], Us[kUpdRows][kLd];
+  __shared__ double s_cs[4];
+  __shared__ double s_red[kThreads / 64];
+  __shared__ int s_flag;
+  const int t = threadIdx.x;
+  const int nch = a.nch;
+  const int64_t plane = (int64_t)a.In * a.ldc;
+  for (int idx = blockIdx.x; idx < a.mt.K * nch; idx += gridDim.x) {
+    const int k = a.mt.order[idx / nch];
+    const int ch = idx % nch;
+    const int r0 = ch * kUpdRows;
+    if (r0 >= a.In) continue;                                     // block-uniform
+    const int R = a.mt.rank[k];
+    const int64_t goff = a.mt.goff[k];
+    double* sc = a.scratch + (int64_t)nch * (goff + 2 * k) + (int64_t)ch * (R * R + 2);
+    const int32_t st = a.status[k];
+    if (st & (JKC_ST_CONVERGED | JKC_ST_NONFINITE)) {            // frozen
+      if (t == 0) sc[R * R + 1] = -1.0;
+      continue;
+    }
+    const int off = a.mt.off[k];
+    const int p = a.mt.left[k];
+    const int rows = min(kUpdRows, a.In - r0);
+    const int zero_row = (a.n == a.nhat && p >= 0) ? p - r0 : -1;
+    // H (other modes' Grams) and the chunk's rows of M: loads issued together
+    build_h(a.G[0], a.G[1], a.G[2], a.G[3], a.N, a.n, goff, R, H);
+    for (int e = t; e < rows * R; e += blockDim.x) {
+      const int i = e / R, r = e % R;
+      const double* src = a.partial + (int64_t)(r0 + i) * a.ldc + off + r;
+      constexpr int kBatch = 16;
+      double m = 0.0;
+      int sp = 0;
+      for (; sp + kBatch <= a.splits; sp += kBatch) {
+        double v[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) v[u] = src[(int64_t)(sp + u) * plane];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) m += v[u];
+      }
+      for (; sp < a.splits; ++sp) m += src[(int64_t)sp * plane];
+      Ms[i][r] = (i == zero_row) ? 0.0 : m;
+    }
+    __syncthreads();
+    const bool chol_ok = cholesky(H, L, R, &s_flag);
+    if (chol_ok)
+      cholesky_inverse(L, Wj, Hp, R);
+    else
+      jacobi_pinv(H, Wj, Vj, Hp, R, s_cs);
+    double inner = 0.0;
+    for (int e = t; e < rows * R; e += blockDim.x) {
+      const int i = e / R, r = e % R;
+      double u = 0.0;
+      for (int q = 0; q < R; ++q) u += Ms[i][q] * Hp[q][r];
+      Us[i][r] = u;
+      a.Utmp[(int64_t)(r0 + i) * a.ldc + off + r] = u;
+      inner += u * Ms[i][r];
+    }
+    const double in_all = block_sum(inner, s_red);   // also makes Us visible
+    // U^T U over the chunk's rows (<= 64: one lane per row), upper triangle
+    {
+      const int wave = t >> 6, lane = t & 63, nw = blockDim.x >> 6;
+      const int npairs = R * (R + 1) / 2;
+      for (int pr = wave; pr < npairs; pr += nw) {
+        int r = 0, rem = pr;
+        while (rem >= R - r) {
+          rem -= R - r;
+          ++r;
+        }
+        const int c = r + rem;
+        double v = lane < rows ? Us[lane][r] * Us[lane][c] : 0.0;
+        v = wave_sum(v);
+        if (lane == 0) sc[r * R + c] = v;
+      }
+    }
+    if (t == 0) {
+      sc[R * R] = in_all;
+      sc[R * R + 1] = chol_ok ? 1.0 : 0.0;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_finalize_rows(const UpdateArgs a) {
+  __shared__ double S[kMaxRank][kLd], Hs[kMaxRank][kLd], Gs[kMaxRank][kLd];
+  __shared__ double lam[kMaxRank];
+  __shared__ double s_in;
+  const int t = threadIdx.x;
+  const int nch = a.nch;
+  const int nchk = (a.In + kUpdRows - 1) / kUpdRows;
+  for (int idx = blockIdx.x; idx < a.mt.K * nch; idx += gridDim.x) {
+    const int k = a.mt.order[idx / nch];
+    const int ch = idx % nch;
+    const int r0 = ch * kUpdRows;
+    if (r0 >= a.In) continue;                                     // block-uniform
+    const int R = a.mt.rank[k];
+    const int64_t goff = a.mt.goff[k];
+    const double* sc0 = a.scratch + (int64_t)nch * (goff + 2 * k);
+    const int stride = R * R + 2;
+    const double flag = sc0[(int64_t)ch * stride + R * R + 1];
+    if (flag < 0.0) continue;                                     // frozen (block-uniform)
+    const int off = a.mt.off[k];
+    const int rows = min(kUpdRows, a.In - r0);
+    // chunk sums in chunk order; the upper triangle of U^T U, then sum U .* M
+    for (int e = t; e <= R * R; e += blockDim.x) {
+      const int r = e / R, c = e % R;
+      if (e < R * R && r > c) continue;
+      double v = 0.0;
+      for (int q = 0; q < nchk; ++q) v += sc0[(int64_t)q * stride + e];
+      if (e == R * R)
+        s_in = v;
+      else
+        S[r][c] = v;
+    }
+    __syncthreads();
+    if (t < R) lam[t] = sqrt(S[t][t]);
+    __syncthreads();
+    for (int e = t; e < rows * R; e += blockDim.x) {
+      const int i = e / R, r = e % R;
+      const int64_t at = (int64_t)(r0 + i) * a.ldc + off + r;
+      const double u = a.Utmp[at];
+      a.U[at] = lam[r] > 0.0 ? u / lam[r] : u;
+    }
+    if (ch == 0) {
+      // Gram of the normalised block over all rows, formed exactly as the
+      // Gram kernel forms it from stored factors (one wavefront per pair,
+      // lanes striding rows, fixed butterfly), so a context restarted from
+      // the factors continues bit for bit.
+      double* Gn = a.n == 0 ? a.G[0] : a.n == 1 ? a.G[1] : a.n == 2 ? a.G[2] : a.G[3];
+      const int wave = t >> 6, lane = t & 63, nw = blockDim.x >> 6;
+      const int npairs = R * (R + 1) / 2;
+      for (int pr = wave; pr < npairs; pr += nw) {
+        int r = 0, rem = pr;
+        while (rem >= R - r) {
+          rem -= R - r;
+          ++r;
+        }
+        const int c = r + rem;
+        double acc = 0.0;
+        for (int i = lane; i < a.In; i += 64) {
+          const double* row = a.Utmp + (int64_t)i * a.ldc + off;
+          const double ur = lam[r] > 0.0 ? row[r] / lam[r] : row[r];
+          const double uc = lam[c] > 0.0 ? row[c] / lam[c] : row[c];
+          acc += ur * uc;
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) {
+          Gn[goff + r * R + c] = acc;
+          Gn[goff + c * R + r] = acc;
+          Gs[r][c] = acc;
+          Gs[c][r] = acc;
+        }
+      }
+      if (t < R) a.lambda[off + t] = lam[t];
+      if (a.last_mode) build_h(a.G[0], a.G[1], a.G[2], a.G[3], a.N, a.n, goff, R, Hs);
+      __syncthreads();
+      if (t == 0) {
+        const int32_t st = a.status[k];
+        int32_t nst = st | (flag > 0.0 ? 0 : JKC_ST_FALLBACK);
+        if (a.last_mode) {
+          double quad = 0.0;
+          for (int r = 0; r < R; ++r)
+            for (int c = 0; c < R; ++c) quad += lam[r] * Hs[r][c] * Gs[r][c] * lam[c];
+          const double nt2 = a.normT2[k];
+          const double e = nt2 + quad - 2.0 * s_in;
+          const double f = 1.0 - sqrt(fmax(e, 0.0)) / sqrt(nt2);
+          const int it = a.iters[k] + 1;
+          a.iters[k] = it;
+          a.err[k] = e;
+          if (!isfinite(e)) nst |= JKC_ST_NONFINITE;
+          if (a.check_conv && a.tol > 0.0 && it >= 2 && fabs(f - a.fit_prev[k]) < a.tol)
+            nst |= JKC_ST_CONVERGED;
+          a.fit_prev[k] = f;
+          a.fit[k] = f;
+        }
+        a.status[k] = nst;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 int persistent_grid(int K) {
   // enough resident blocks to cover all 256 compute units a few times over
   return K < 1024 ? K : 1024;
@@ -780,6 +983,17 @@ hipError_t launch_update(const UpdateArgs& a, hipStream_t s) {
   } else {
     hipLaunchKernelGGL(k_update, dim3(persistent_grid(a.mt.K)), dim3(kThreads), 0, s, a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_update_rows(const UpdateArgs& a, hipStream_t s) {
+  if (a.mt.K <= 0) return hipSuccess;
+  const int64_t work = (int64_t)a.mt.K * a.nch;
+  const int blocks = (int)(work < 4096 ? work : 4096);
+  hipLaunchKernelGGL(k_solve_rows, dim3(blocks), dim3(kThreads), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finalize_rows, dim3(blocks), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
