@@ -375,7 +375,9 @@ __global__ void __launch_bounds__(kThreads) k_update_lds(const UpdateArgs a) {
   const int64_t plane = (int64_t)a.In * a.ldc;
 
   for (int idx = blockIdx.x; idx < a.mt.K; idx += gridDim.x) {
-    const int k = a.mt.order[idx];
+    // one model per block when the grid covers them all (the cost order only
+    // matters for a persistent grid): saves a dependent load
+    const int k = (int)gridDim.x >= a.mt.K ? idx : a.mt.order[idx];
     const int32_t st = a.status[k];
     if (st & (JKC_ST_CONVERGED | JKC_ST_NONFINITE)) continue;  // frozen (block-uniform)
     const int R = a.mt.rank[k];
@@ -594,13 +596,20 @@ __global__ void __launch_bounds__(kThreads) k_update_lds(const UpdateArgs a) {
     }
     if (t < R) a.lambda[off + t] = lam[t];
     __syncthreads();
+    // the error's quadratic form lambda^T (H * G) lambda: wavefront 0, lanes
+    // over the R^2 terms, fixed butterfly
+    double quad = 0.0;
+    if (a.last_mode && t < 64) {
+      for (int e = t; e < R * R; e += 64) {
+        const int r = e / R, c = e % R;
+        quad += lam[r] * H[r * ld + c] * Gs[r * ld + c] * lam[c];
+      }
+      quad = wave_sum(quad);
+    }
     if (t == 0) {
       int32_t nst = st | (chol_ok ? 0 : JKC_ST_FALLBACK);
       if (a.last_mode) {
         const double in = in_all;
-        double quad = 0.0;
-        for (int r = 0; r < R; ++r)
-          for (int c = 0; c < R; ++c) quad += lam[r] * H[r * ld + c] * Gs[r * ld + c] * lam[c];
         const double nt2 = pre_nt2;
         const double e = nt2 + quad - 2.0 * in;
         const double f = 1.0 - sqrt(fmax(e, 0.0)) / sqrt(nt2);
