@@ -48,7 +48,49 @@ def parse():
                     help="c2: the benchmark workload (default); c3/c4: the uneven-batch and "
                          "split-precision workloads, for kernel measurements")
     ap.add_argument("--precision", default=None, choices=["fp64", "bf16x3", "bf16x6"])
+    ap.add_argument("--efficiency-sweep", action="store_true",
+                    help="instead of the benchmark: fused MTTKRP efficiency against the column "
+                         "count C on a 50x200x200 tensor (the analogue of the paper's Fig. 1); "
+                         "prints one JSON line per (C, mode)")
     return ap.parse_args()
+
+
+def efficiency_sweep():
+    """Fused float64 MTTKRP TFLOP/s against C on 50 x 200 x 200 (Sec. 4.2's
+    experiment shape): models of rank 5 (the last one narrower) side by side,
+    tilings tuned per C, kernel time from HIP events on the context stream."""
+    import numpy as np
+    import torch
+
+    import paper_2112_03985_amd as jk
+
+    shape = (50, 200, 200)
+    P = int(np.prod(shape))
+    rng = np.random.default_rng(211203985)
+    T = jk.to_device_tensor(np.asfortranarray(rng.standard_normal(shape)))
+    for C in (1, 2, 5, 10, 20, 50, 100, 200, 500, 1000):
+        ranks = [5] * (C // 5) + ([C % 5] if C % 5 else [])
+        init = [torch.from_numpy(rng.standard_normal((I, C))).cuda() for I in shape]
+        ctx = jk.JkCals(T, shape, 0, ranks, [-1] * len(ranks), init)
+        ctx.tune(3)
+        out = torch.empty((max(shape), C), dtype=torch.float64, device="cuda")
+        for n in range(3):
+            for _ in range(2):
+                ctx.mttkrp(n, out[:shape[n]])
+            torch.cuda.synchronize()
+            ctx.profile(True)
+            for _ in range(10):
+                ctx.mttkrp(n, out[:shape[n]])
+            cnt, ms = ctx.profile_read()
+            ctx.profile(False)
+            kms = float(ms[n] / max(cnt[n], 1))
+            tf = 2.0 * C * P / (kms * 1e-3) / 1e12
+            print(json.dumps({"experiment": "mttkrp_efficiency_vs_C", "dims": list(shape), "C": C,
+                              "mode": n, "kernel_ms": round(kms, 5), "tflops": round(tf, 3),
+                              "frac_fp64_peak": round(tf / PEAK_FP64_TFLOPS, 4),
+                              "tiling": ctx.describe(n)}), flush=True)
+        del ctx
+    return 0
 
 
 def measured_traffic(workload, prec_name, desc):
@@ -91,6 +133,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
+    if args.efficiency_sweep:
+        return efficiency_sweep()
     if args.workload == "c2":
         wl = synth.config2()
         desc_w = ("c2: 100x200x200 f64 fluorescence-like tensor, rank 5, 2%% noise; "
