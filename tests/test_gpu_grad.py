@@ -112,3 +112,44 @@ def test_refinement_matches_oracle():
         Up = r.padded(Ur)
         for n in range(3):
             assert rel(facs[n][:, cols(wl, k)], Up[n]) <= 1e-10, (k, n)
+
+
+def test_config5_full_size_gradient_and_refinement():
+    """Refinement workload at full size (100x150x150 tensor stored as
+    float32, rank 10, 100 leave-one-out models, C = 1000): after ALS sweeps,
+    the loss and the all-mode gradient of sampled models against the oracle
+    on their reduced tensors, then gradient refinement against the oracle
+    running the same rule."""
+    import torch
+    wl = synth.config5()
+    sweeps, steps = 3, 20
+    models = [0, 57, 99]
+    say("c5 full size: gradient and refinement")
+    ctx = make_ctx(wl)
+    ctx.sweep(sweeps)
+    loss = torch.empty(wl.K, dtype=torch.float64, device="cuda")
+    ctx.loss_grad(loss)
+    L = to_np(loss)
+    G = [to_np(ctx.get_grad(n)) for n in range(3)]
+    ctx.refine(steps)
+    facs = [to_np(ctx.get_factors(n)[0]) for n in range(3)]
+    T = np.asarray(wl.T, dtype=np.float64)
+    res = oracle.jk_als(T, 0, wl.ranks, wl.left_out, wl.init, sweeps, models=models)
+    for k in models:
+        r = res[k]
+        U = [u.copy() for u in r.U]
+        U[-1] = U[-1] * r.lam[None, :]
+        Tk = oracle.reduce_tensor(T, 0, int(wl.left_out[k]))
+        f, g = oracle.loss_and_grad(Tk, U)
+        normT = np.sqrt(np.sum(Tk ** 2))
+        assert abs(L[k] - f) <= 1e-10 * max(1.0, 0.5 * normT ** 2), (k, L[k], f)
+        gp = r.padded(g)
+        for n in range(3):
+            # the last updated mode's gradient is zero up to rounding, so the
+            # error is measured against the size of the MTTKRP it cancels
+            scale = normT * np.prod([np.linalg.norm(U[m]) for m in range(3) if m != n])
+            err = np.linalg.norm(G[n][:, cols(wl, k)] - gp[n])
+            assert err <= 1e-11 * max(scale, np.linalg.norm(gp[n])), (k, n, err, scale)
+        Up = r.padded(oracle.gd_refine(Tk, U, steps))
+        for n in range(3):
+            assert rel(facs[n][:, cols(wl, k)], Up[n]) <= 1e-10, (k, n)
