@@ -24,6 +24,9 @@ namespace jkc {
 namespace {
 
 constexpr int kThreads = 256;
+// block size of the LDS-staged update: its row phases (U = M H^{-1}, column
+// norms, Gram pairs) are spread over more wavefronts
+constexpr int kUpdThreads = 512;
 constexpr int kLd = kMaxRank + 1;   // LDS row pitch of R x R matrices
 
 __device__ inline double wave_sum(double v) {
@@ -356,7 +359,7 @@ __global__ void __launch_bounds__(kThreads) k_update(const UpdateArgs a) {
 // LDS, so global memory is touched once for reading and once for writing.
 // Used when the model's rows fit in the dynamic LDS budget.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) k_update_lds(const UpdateArgs a) {
+__global__ void __launch_bounds__(kUpdThreads) k_update_lds(const UpdateArgs a) {
   extern __shared__ double smem[];
   const int Rp = a.rmax;
   const int ld = Rp + 1;
@@ -367,8 +370,8 @@ __global__ void __launch_bounds__(kThreads) k_update_lds(const UpdateArgs a) {
   double* Gs = V + Rp * ld;            // new Gram block
   double* lam = Gs + Rp * ld;
   double* misc = lam + Rp;             // [0] c, [1] s, [2] done, [3] cutoff
-  double* red = misc + 8;              // per-thread partial of the error's inner product
-  double* Ms = red + kThreads;         // In x ld: reduced M block
+  double* red = misc + 8;              // per-wavefront sums (block_sum)
+  double* Ms = red + kUpdThreads / 64; // In x ld: reduced M block
   double* Us = Ms + (size_t)a.In * ld; // In x ld: U block
   __shared__ int s_flag;
   const int t = threadIdx.x;
@@ -410,12 +413,33 @@ __global__ void __launch_bounds__(kThreads) k_update_lds(const UpdateArgs a) {
       }
       H[r * ld + c] = h;
     }
-    for (int e = t; e < a.In * R; e += blockDim.x) {
-      const int i = e / R, r = e % R;
-      const double* src = a.partial + (int64_t)i * a.ldc + off + r;
-      double m = 0.0;
-      for (int sp = 0; sp < a.splits; ++sp) m += src[sp * plane];
-      Ms[i * ld + r] = (i == zero_row) ? 0.0 : m;
+    // M: kStage elements per thread per round, their loads issued before
+    // any of them is stored (one memory latency per round, not one per
+    // element); partials summed in ascending split order
+    {
+      constexpr int kStage = 4;
+      const int nel = a.In * R;
+      for (int e0 = 0; e0 < nel; e0 += kStage * (int)blockDim.x) {
+        double m[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+          const int e = e0 + u * (int)blockDim.x + t;
+          m[u] = 0.0;
+          if (e < nel) {
+            const int i = e / R, r = e - (e / R) * R;
+            const double* src = a.partial + (int64_t)i * a.ldc + off + r;
+            for (int sp = 0; sp < a.splits; ++sp) m[u] += src[sp * plane];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+          const int e = e0 + u * (int)blockDim.x + t;
+          if (e < nel) {
+            const int i = e / R, r = e - (e / R) * R;
+            Ms[i * ld + r] = (i == zero_row) ? 0.0 : m[u];
+          }
+        }
+      }
     }
     __syncthreads();
 
@@ -980,14 +1004,14 @@ int grid_for(int64_t n) {
 
 int64_t update_lds_doubles(int rmax, int rows) {
   const int64_t ld = rmax + 1;
-  return 5 * rmax * ld + rmax + 8 + kThreads + 2 * (int64_t)rows * ld;
+  return 5 * rmax * ld + rmax + 8 + kUpdThreads / 64 + 2 * (int64_t)rows * ld;
 }
 
 hipError_t launch_update(const UpdateArgs& a, hipStream_t s) {
   if (a.mt.K <= 0) return hipSuccess;
   if (a.lds_doubles > 0) {
     int blocks = a.mt.K < 2048 ? a.mt.K : 2048;
-    hipLaunchKernelGGL(k_update_lds, dim3(blocks), dim3(kThreads),
+    hipLaunchKernelGGL(k_update_lds, dim3(blocks), dim3(kUpdThreads),
                        (size_t)a.lds_doubles * sizeof(double), s, a);
   } else {
     hipLaunchKernelGGL(k_update, dim3(persistent_grid(a.mt.K)), dim3(kThreads), 0, s, a);
