@@ -211,7 +211,9 @@ int32_t jk_cals_num_tilings(jkc_ctx *ctx);
 
 /* Force tiling `variant` (0 .. num_tilings-1) with `splits` K chunks
  * (clamped to 1 .. the context's limit) for `mode`.  Any tiling gives the
- * same result up to the order of the float64 sums.  Host only. */
+ * same result up to the order of the float64 sums.  JKC_EINVAL for a
+ * buffer-load tiling (its description ends in "-buffer") when the tensor or
+ * a multi-factor takes 2^31 bytes or more.  Host only. */
 jkc_status jk_cals_set_tiling(jkc_ctx *ctx, int32_t mode, int32_t variant, int32_t splits);
 
 /* Kernel timing of the fused MTTKRP (the dominant kernel): while enabled,

@@ -35,6 +35,15 @@
 //      instruction is a 4 x 16 x 4 step and tiles need only multiples of 4
 //      rows (no padding of 100- or 200-row modes to 16).
 // INSTR + 8 selects the interleaved step schedule (see the main loop).
+// INSTR + 16 loads through buffer resources with 32-bit byte offsets (the
+// tensor and every factor below 2^31 bytes): the hardware range check
+// returns zeros past the end, so the chunk end is enforced by pointing the
+// Khatri-Rao loads of out-of-range K indices past their buffer, and tile
+// rows and columns past the matrix read clamped-free (their results are
+// never stored).  Row offsets are scalar and immediate, so a step spends
+// almost no vector instructions on addressing and masking: on gfx950 every
+// vector ALU instruction issued between matrix instructions costs matrix
+// throughput.
 // Partials of the K chunks are summed later in a fixed order, so results are
 // bitwise repeatable for a fixed tiling.
 #include <type_traits>
@@ -86,6 +95,11 @@ struct ColWalker {
     return (int64_t)idx[0] * a.ostride[0] + (int64_t)idx[1] * a.ostride[1] +
            (int64_t)idx[2] * a.ostride[2];
   }
+  // the same offset in 32-bit arithmetic (tensors below 2^31 bytes)
+  __device__ uint32_t toff32(const MttkrpArgs& a) const {
+    return idx[0] * (uint32_t)a.ostride[0] + idx[1] * (uint32_t)a.ostride[1] +
+           idx[2] * (uint32_t)a.ostride[2];
+  }
 };
 
 template <int WM, int WN, int TM, int TN, int BK, int INSTR, int NO, bool F32>
@@ -94,6 +108,7 @@ k_mttkrp_f64(const MttkrpArgs a) {
   constexpr int NT = 64 * WM * WN;
   constexpr int FAM = INSTR & 7;             // matrix instruction family
   constexpr bool SCHED = (INSTR & 8) != 0;   // interleaved step schedule
+  constexpr bool BUF = (INSTR & 16) != 0;    // buffer loads, 32-bit offsets
   constexpr int RPT = FAM == 2 ? 4 : 16;     // rows per matrix-core tile
   constexpr int BM = WM * TM * RPT;
   // rows staged in LDS: a multiple of 16, and of the rows one K index of a
@@ -172,12 +187,56 @@ k_mttkrp_f64(const MttkrpArgs a) {
   // the step is stored, so no load result is consumed (waited for) before
   // the matrix-core work of the current step has been issued.
   using TT = typename std::conditional<F32, float, double>::type;
+  using TTyp = TT;
   TT ra[VA];
   double rb[NO][VB];
   uint32_t amask = 0;
   uint32_t bmask = 0;
 
+  // Buffer resources (word 3: the gfx9 raw-buffer format, range checked).
+  constexpr int kRsrcWord3 = 0x00020000;
+  const __amdgpu_buffer_rsrc_t rT = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void*>(a.T), (short)0, BUF ? (int)((int64_t)a.M * a.J * (int64_t)sizeof(TTyp)) : 0,
+      kRsrcWord3);
+  __amdgpu_buffer_rsrc_t rU[NO];
+#pragma unroll
+  for (int q = 0; q < NO; ++q)
+    rU[q] = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(a.oU[q]), (short)0,
+                                              BUF ? a.odim[q] * a.ldc * 8 : 0, kRsrcWord3);
+  // byte distance between a thread's consecutive A rows (scalar)
+  const int sA_bytes = (int)(sA * a.stride_n * (int64_t)sizeof(TTyp));
+
   auto load_step = [&]() {
+    if constexpr (BUF) {
+      const uint32_t voffA = (wA.toff32(a) + (uint32_t)(i0 + gA) * (uint32_t)a.stride_n) *
+                             (uint32_t)sizeof(TTyp);
+#pragma unroll
+      for (int v = 0; v < VA; ++v) {
+        if constexpr (F32)
+          ra[v] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rT, voffA, v * sA_bytes, 0));
+        else
+          ra[v] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rT, voffA, v * sA_bytes, 0));
+      }
+      // K indices past the chunk read past the factor buffers (zeros)
+      const bool kok = wB.j < kend;
+#pragma unroll
+      for (int q = 0; q < NO; ++q) {
+        const uint32_t vb = kok ? (wB.idx[q] * (uint32_t)a.ldc + (uint32_t)(c0 + PB * gB)) * 8u
+                                : 0x80000000u;
+#pragma unroll
+        for (int u = 0; u < VB / PB; ++u) {
+          const uint32_t o = vb + (uint32_t)(8 * PB * GB * u);
+          if constexpr (PB == 2) {
+            const double2 x = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rU[q], o, 0, 0));
+            rb[q][2 * u] = x.x;
+            rb[q][2 * u + 1] = x.y;
+          } else {
+            rb[q][u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rU[q], o, 0, 0));
+          }
+        }
+      }
+      return;
+    }
     const bool va = wA.j < kend;
     const int64_t toffA = va ? wA.toff(a) : 0;
     amask = 0;
@@ -228,7 +287,7 @@ k_mttkrp_f64(const MttkrpArgs a) {
       for (int v = 0; v < VB; ++v) asm volatile("" : "+v"(rb[q][v]));
 #pragma unroll
     for (int v = 0; v < VA; ++v)
-      As[buf][kA][gA + sA * v] = (amask >> v) & 1u ? (double)ra[v] : 0.0;
+      As[buf][kA][gA + sA * v] = (BUF || ((amask >> v) & 1u)) ? (double)ra[v] : 0.0;
 #pragma unroll
     for (int u = 0; u < VB / PB; ++u) {
       double x[PB];
@@ -238,7 +297,7 @@ k_mttkrp_f64(const MttkrpArgs a) {
         double y = rb[NO - 1][PB * u + p];
 #pragma unroll
         for (int q = NO - 2; q >= 0; --q) y *= rb[q][PB * u + p];
-        x[p] = (bmask >> u) & 1u ? y : 0.0;
+        x[p] = (BUF || ((bmask >> u) & 1u)) ? y : 0.0;
       }
       double* dst = &Bs[buf][kB][PB * (gB + GB * u)];
       if constexpr (PB == 2)
@@ -277,12 +336,14 @@ k_mttkrp_f64(const MttkrpArgs a) {
   auto read_frag = [&](int buf, int kk, int slot) {
     if constexpr (FAM == 2) {
       // row strips: every block gets the same 4 rows of A (same LDS
-      // addresses), block b the columns 4b..4b+3 of each 16-column group
-#pragma unroll
-      for (int x = 0; x < TM; ++x) fa[slot][x] = As[buf][kk + kq4][wm * TM * 4 + x * 4 + e4];
+      // addresses), block b the columns 4b..4b+3 of each 16-column group.
+      // B first, then A in the order the matrix instructions use them, so
+      // the first instructions of a group wait only for the earliest reads.
 #pragma unroll
       for (int y = 0; y < TN; ++y)
         fb[slot][y] = Bs[buf][kk + kq4][wn * TN * 16 + y * 16 + 4 * b4 + e4];
+#pragma unroll
+      for (int x = 0; x < TM; ++x) fa[slot][x] = As[buf][kk + kq4][wm * TM * 4 + x * 4 + e4];
     } else if constexpr (FAM == 0) {
 #pragma unroll
       for (int x = 0; x < TM; ++x) fa[slot][x] = As[buf][kk + blk][wm * TM * 16 + x * 16 + o16];
@@ -319,30 +380,41 @@ k_mttkrp_f64(const MttkrpArgs a) {
   // One K step = G groups of matrix-core work.  Loads and the store of the
   // next step run unconditionally (past the end of the chunk they fetch
   // clamped addresses and store zeros into the idle buffer), which keeps the
-  // step free of branches; the store goes into the other LDS buffer, free
-  // since the last barrier, before the final group.
+  // step free of branches.
   //
   // Interleaved schedule (SCHED): each group is a scheduling region of its
   // own in which the step's memory work is interleaved with the matrix
   // instructions by scheduling-group directives (one global load, one LDS
   // read, or one LDS write with its arithmetic between matrix instructions)
-  // and the fragments of group g+1 are read while group g computes.
+  // and the fragments of group g+1 are read while group g computes.  The
+  // next step is stored into the other LDS buffer during group G-2 and the
+  // step's barrier sits before the last group, whose fragments are already
+  // in registers: the first fragments of the next step are read from the
+  // other buffer while the last group computes, so no wavefront waits on
+  // LDS right after the barrier.
   // Otherwise the compiler schedules each group; scheduling barriers only
   // keep the loads at the head of the step and the store before the last
-  // group.
+  // group, and the barrier ends the step.
+  static_assert(!SCHED || (G >= 4 && G % 2 == 0), "interleaved schedule needs BK % 16 == 0");
+  if constexpr (SCHED) {
+    if (nsteps > 0) read_frag(0, 0, 0);
+  }
   for (int s = 0; s < nsteps; ++s) {
     const int buf = s & 1;
     if constexpr (SCHED) {
-      read_frag(buf, 0, 0);
-      __builtin_amdgcn_sched_barrier(0);
       wA.advance(a, BK);
       wB.advance(a, BK);
       load_step();
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         const int cur = g & 1;
-        if (g + 1 < G) read_frag(buf, 4 * (g + 1), cur ^ 1);
-        else store_step(buf ^ 1);
+        if (g == G - 1) {
+          __syncthreads();
+          read_frag(buf ^ 1, 0, cur ^ 1);
+        } else {
+          read_frag(buf, 4 * (g + 1), cur ^ 1);
+          if (g == G - 2) store_step(buf ^ 1);
+        }
         mfma_group(cur);
         if (g == 0) {
 #pragma unroll
@@ -351,18 +423,23 @@ k_mttkrp_f64(const MttkrpArgs a) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // matrix
           }
         }
-        if (g + 1 < G) {
+        if (g == G - 2) {
 #pragma unroll
           for (int i = 0; i < NRD; ++i) {
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
-            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // matrix
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // matrix
           }
-        } else {
 #pragma unroll
           for (int i = 0; i < VA + VB / PB; ++i) {
             __builtin_amdgcn_sched_group_barrier(0x002, 2 * NO, 0);   // products, selects
             __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);       // LDS write
-            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);       // matrix
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);       // matrix
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < NRD; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // matrix
           }
         }
         __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);
@@ -383,8 +460,8 @@ k_mttkrp_f64(const MttkrpArgs a) {
         read_frag(buf, 4 * g, 0);
         mfma_group(0);
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   // Epilogue.  16x16x4: lane l holds, in element r, row 4*r + l/16 and
@@ -481,6 +558,16 @@ const std::vector<MttkrpVariant>& mttkrp_f64_variants() {
       JKC_F64_VARIANT(4, 2, 13, 2, 32, 10), // 208 x 64, 8 wavefronts, BK 32
       JKC_F64_VARIANT(2, 4, 13, 4, 16, 10), // 104 x 256, 8 wavefronts
       JKC_F64_VARIANT(2, 4, 4, 2, 16, 8),   // 128 x 128, 8 wavefronts, 16x16x4
+      // interleaved schedule, buffer loads
+      JKC_F64_VARIANT(2, 4, 13, 2, 32, 26), // 104 x 128, 8 wavefronts, BK 32
+      JKC_F64_VARIANT(2, 4, 13, 2, 16, 26), // 104 x 128, 8 wavefronts
+      JKC_F64_VARIANT(2, 2, 13, 4, 16, 26), // 104 x 128
+      JKC_F64_VARIANT(2, 2, 13, 2, 16, 26), // 104 x 64
+      JKC_F64_VARIANT(4, 2, 7, 4, 32, 26),  // 112 x 128, 8 wavefronts, BK 32
+      JKC_F64_VARIANT(4, 2, 13, 2, 32, 26), // 208 x 64, 8 wavefronts, BK 32
+      JKC_F64_VARIANT(2, 4, 13, 4, 16, 26), // 104 x 256, 8 wavefronts
+      JKC_F64_VARIANT(1, 4, 7, 2, 16, 24),  // 112 x 128, 16x16x4
+      JKC_F64_VARIANT(2, 4, 4, 2, 16, 24),  // 128 x 128, 8 wavefronts, 16x16x4
   };
   return v;
 }

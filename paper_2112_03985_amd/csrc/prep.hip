@@ -4,6 +4,8 @@
 // inserted zero row of Alg. 3's initialisation, the fixed-order reduction of
 // split-K MTTKRP partials with the Case I row removal, and the explicit
 // slice removal of Alg. 2 (used by the plain per-submodel baseline).
+#include <algorithm>
+
 #include "jkc_internal.hpp"
 
 namespace jkc {
@@ -179,33 +181,56 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
     p[e] = v;
 }
 
-// out[i][c] = sum_s partial[s][i][c] in ascending s; row colp[c] set to 0
-// when zero_rows (Case I: the left-out row of the sampled mode's MTTKRP).
-__global__ void k_reduce(const double* partial, int32_t splits, int32_t rows, int32_t ldc,
-                         int32_t ncols, const int32_t* colp, int32_t zero_rows, double* out,
-                         int32_t ldo) {
+// out[i][c] = sum_s partial[s][i][c]; row colp[c] set to 0 when zero_rows
+// (Case I: the left-out row of the sampled mode's MTTKRP).  A block covers
+// 64 consecutive elements with kReduceGroups wavefronts: with many partials
+// wavefront q sums its contiguous quarter of the splits in ascending order
+// and the quarter sums are added in ascending q; with few partials
+// (splits < kReduceQuarterMin) wavefront 0 sums them all in ascending order.
+// Either order is fixed, so the result is bitwise repeatable.
+constexpr int kReduceGroups = 4;
+constexpr int kReduceQuarterMin = 16;
+__global__ void __launch_bounds__(64 * kReduceGroups)
+k_reduce(const double* partial, int32_t splits, int32_t rows, int32_t ldc, int32_t ncols,
+         const int32_t* colp, int32_t zero_rows, double* out, int32_t ldo) {
+  __shared__ double part[kReduceGroups][64];
   const int64_t n = (int64_t)rows * ncols;
   const int64_t plane = (int64_t)rows * ldc;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e / ncols;
-    const int c = (int)(e % ncols);
-    const int64_t at = i * ldc + c;
-    // Loads of kBatch partials are issued together (they are independent),
-    // the additions still run in ascending split order.
-    constexpr int kBatch = 16;
+  const int lane = threadIdx.x & 63;
+  const int q = threadIdx.x >> 6;
+  const int groups = splits >= kReduceQuarterMin ? kReduceGroups : 1;
+  const int per = (splits + groups - 1) / groups;
+  const int sb = q * per;
+  const int se = min(splits, sb + per);
+  for (int64_t e0 = (int64_t)blockIdx.x * 64; e0 < n; e0 += (int64_t)gridDim.x * 64) {
+    const int64_t e = e0 + lane;
+    const bool ok = e < n;
+    const int64_t i = ok ? e / ncols : 0;
+    const int c = ok ? (int)(e % ncols) : 0;
+    const double* src = partial + i * ldc + c;
     double s = 0.0;
-    int sp = 0;
-    for (; sp + kBatch <= splits; sp += kBatch) {
-      double v[kBatch];
+    if (ok && q < groups) {
+      // loads of kBatch partials issued together, additions in ascending order
+      constexpr int kBatch = 8;
+      int sp = sb;
+      for (; sp + kBatch <= se; sp += kBatch) {
+        double v[kBatch];
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) v[u] = partial[(int64_t)(sp + u) * plane + at];
+        for (int u = 0; u < kBatch; ++u) v[u] = src[(int64_t)(sp + u) * plane];
 #pragma unroll
-      for (int u = 0; u < kBatch; ++u) s += v[u];
+        for (int u = 0; u < kBatch; ++u) s += v[u];
+      }
+      for (; sp < se; ++sp) s += src[(int64_t)sp * plane];
     }
-    for (; sp < splits; ++sp) s += partial[(int64_t)sp * plane + at];
-    if (zero_rows && colp[c] == (int)i) s = 0.0;
-    out[i * ldo + c] = s;
+    part[q][lane] = s;
+    __syncthreads();
+    if (q == 0 && ok) {
+      double t = part[0][lane];
+      for (int g = 1; g < groups; ++g) t += part[g][lane];
+      if (zero_rows && colp[c] == (int)i) t = 0.0;
+      out[i * ldo + c] = t;
+    }
+    __syncthreads();
   }
 }
 
@@ -302,7 +327,10 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
 hipError_t launch_reduce(const double* partial, int32_t splits, int32_t rows, int32_t ldc,
                          int32_t ncols, const int32_t* colp, int32_t zero_rows, double* out,
                          int32_t ldo, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(grid_for((int64_t)rows * ncols)), dim3(256), 0, s, partial,
+  const int64_t n = (int64_t)rows * ncols;
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 63) / 64, 16384);
+  hipLaunchKernelGGL(k_reduce, dim3((unsigned)blocks), dim3(64 * kReduceGroups), 0, s, partial,
                      splits, rows, ldc, ncols, colp, zero_rows, out, ldo);
   return hipGetLastError();
 }

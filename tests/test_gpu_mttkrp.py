@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import synth
+import paper_2112_03985_amd as jk
 from gpu_util import make_ctx, oracle_model_mttkrp, rel, say, to_np, cols
 
 pytestmark = pytest.mark.gpu
@@ -41,13 +42,18 @@ def test_fused_mttkrp_matches_per_model(spec):
     say("worst rel err", worst)
 
 
-def test_every_tiling_matches():
-    wl = synth.random_problem(11, (67, 31, 26), [5, 9, 2], [-1, 66, 3], noise=0.1)
+@pytest.mark.parametrize("dims,dtype,split_list", [
+    ((67, 31, 26), np.float64, (1, 3, 8)),
+    ((19, 13, 11, 7), np.float32, (1, 5)),   # three other modes, float32 storage
+])
+def test_every_tiling_matches(dims, dtype, split_list):
+    wl = synth.random_problem(11, dims, [5, 9, 2], [-1, dims[0] - 1, 3], noise=0.1, dtype=dtype)
     ctx = make_ctx(wl)
-    refs = {(n, k): oracle_model_mttkrp(wl, k, n) for n in range(3) for k in range(wl.K)}
+    N = len(dims)
+    refs = {(n, k): oracle_model_mttkrp(wl, k, n) for n in range(N) for k in range(wl.K)}
     for v in range(ctx.num_tilings()):
-        for splits in (1, 3, 8):
-            for n in range(3):
+        for splits in split_list:
+            for n in range(N):
                 say("tiling", v, splits, n)
                 ctx.set_tiling(n, v, splits)
                 M = to_np(ctx.mttkrp(n))
@@ -104,3 +110,29 @@ def test_case_I_row_is_zero_and_full_model_row_is_not():
     M = to_np(ctx.mttkrp(0))
     assert np.all(M[4, 2:4] == 0.0)
     assert np.all(M[4, 0:2] != 0.0)
+
+
+def test_tensor_past_2_gib_uses_64_bit_addressing():
+    """A float64 tensor of 2^31 bytes or more (1024 x 1024 x 264, 2.2 GB)
+    cannot use the buffer-load tilings (32-bit byte offsets): the default
+    choice avoids them, the MTTKRP still matches the oracle, and forcing a
+    buffer-load tiling is refused."""
+    wl = synth.random_problem(15, (1024, 1024, 264), [2, 3], [-1, 5], noise=0.1)
+    say("2 GiB tensor")
+    ctx = make_ctx(wl, copy_tensor=False)
+    for n in (0, 2):
+        assert not ctx.describe(n).endswith("-buffer"), ctx.describe(n)
+        M = to_np(ctx.mttkrp(n))
+        for k in range(wl.K):
+            e = rel(M[:, cols(wl, k)], oracle_model_mttkrp(wl, k, n))
+            assert e <= TOL, (n, k, e, ctx.describe(n))
+    refused = 0
+    for v in range(ctx.num_tilings()):
+        try:
+            ctx.set_tiling(0, v, 1)
+        except jk.JkcError as e:
+            assert "2^31 bytes" in str(e)
+            refused += 1
+        else:
+            assert not ctx.describe(0).endswith("-buffer")
+    assert refused > 0
