@@ -17,6 +17,9 @@ What it computes, and from which passage:
                    row removal steps followed by CP-ALS), per-iteration
                    records, the CP least-squares loss and its gradient, the
                    gradient-refinement rule, and the flop counts of Sec. 4.2.
+* ``postprocess`` -- the end of Alg. 2: permutation and scale adjustment of
+                   every submodel against the overall model, and the
+                   standard deviation of the factors over the submodels.
 
 JK-CALS (Alg. 3) changes performance, not the numerics: by Case I and
 Case II of Sec. 4.1 its fused MTTKRP equals each submodel's own MTTKRP on the
@@ -35,7 +38,11 @@ Readings of passages that are silent or garbled (each repeated where used):
   2-norm and the norms kept as lambda (absent from the paper, standard
   practice, does not change the fitted model);
 * fit = 1 - ||T - [[lambda; U]]|| / ||T||, convergence when |delta fit| < tol;
-* Gram matrices are made exactly symmetric by mirroring the upper triangle.
+* Gram matrices are made exactly symmetric by mirroring the upper triangle;
+* jackknife post-processing: matching by the product over the non-sampled
+  modes of the column cosines (exact assignment), unit-norm columns with
+  signs aligned to the reference, and the jackknife standard deviation
+  sqrt((K-1)/K * sum (theta - mean)^2).
 
 Parity status of each function is stated in its docstring; the pins that tie
 it to the paper and to mathematics live in ``tests/test_oracle_*.py``.
@@ -46,6 +53,7 @@ from .cp import (unfold, khatri_rao, krp_excluding, mttkrp, mttkrp_bruteforce,
 from .jackknife import (reduce_tensor, reduce_init, cp_als, jk_als, loss, grad,
                         loss_and_grad, fd_grad, gd_refine, flops_jk_als,
                         flops_jk_cals, flop_ratio, model_offsets, ModelResult)
+from .postprocess import congruence, match_components, aligned_factors, jackknife_std
 
 __all__ = [
     "unfold", "khatri_rao", "krp_excluding", "mttkrp", "mttkrp_bruteforce",
@@ -53,5 +61,5 @@ __all__ = [
     "error_fast", "reconstruct", "residual_explicit", "reduce_tensor",
     "reduce_init", "cp_als", "jk_als", "loss", "grad", "loss_and_grad", "fd_grad",
     "gd_refine", "flops_jk_als", "flops_jk_cals", "flop_ratio", "model_offsets",
-    "ModelResult",
+    "ModelResult", "congruence", "match_components", "aligned_factors", "jackknife_std",
 ]
