@@ -232,6 +232,26 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         with_reduce_ms.append(e0.elapsed_time(e1) / 5)
+    # jackknife post-processing (Alg. 2: matching, scale adjustment and the
+    # standard deviations) of one set of fitted submodels: the leave-one-out
+    # run after the first model, against the full model when there is one
+    # (else against the first submodel), at most one per left-out sample
+    ref = 0
+    s0 = 1 if int(wl.left_out[0]) < 0 and K > 1 else 0
+    cnt = 0
+    while (s0 + cnt < K and cnt < wl.dims[0] and int(wl.ranks[s0 + cnt]) == int(wl.ranks[ref])
+           and int(wl.left_out[s0 + cnt]) >= 0):
+        cnt += 1
+    jk_ms = None
+    if cnt > 0:
+        c.jackknife_std(ref, s0, cnt)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            c.jackknife_std(ref, s0, cnt)
+        e1.record()
+        torch.cuda.synchronize()
+        jk_ms = e0.elapsed_time(e1) / 5
     del c, mout
     # context init alone (tensor copy or split, slice norms, packing, Grams)
     torch.cuda.synchronize()
@@ -273,7 +293,9 @@ def main():
            "mttkrp_with_reduce": {
                "per_mode_ms": [round(x, 5) for x in with_reduce_ms],
                "tflops": round(flops_per_launch / (float(np.mean(with_reduce_ms)) * 1e-3) / 1e12, 3)},
-           "fit_range": [round(float(fit.min()), 6), round(float(fit.max()), 6)]}
+           "fit_range": [round(float(fit.min()), 6), round(float(fit.max()), 6)],
+           "jackknife_postprocess": {"ms": None if jk_ms is None else round(jk_ms, 4),
+                                     "reference_model": ref, "submodels": cnt}}
 
     if not args.no_plain:
         print("[bench] plain per-submodel ALS on the GPU (%d models)" % args.plain_models,

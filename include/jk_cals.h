@@ -179,6 +179,34 @@ jkc_status jk_cals_get_grad(jkc_ctx *ctx, int32_t mode, const double *weights,
  * Asynchronous. */
 jkc_status jk_cals_refine(jkc_ctx *ctx, int32_t steps, double *loss);
 
+/* Jackknife uncertainty of the factors (Alg. 2: the permutation and scale
+ * adjustment of every fitted submodel against the overall model, then the
+ * standard deviation of each factor matrix except the sampled mode's over
+ * the submodels), from the context's current factors.
+ *   ref:   index of the reference model (normally the one with
+ *          left_out = -1, fitted to all of T);
+ *   first, count: the set of submodels, models first .. first+count-1, all
+ *          of the reference's rank R (their columns are contiguous);
+ *   std:   host array[N] of device pointers; std[n] (n != sampled mode)
+ *          receives S_n, I_n x R row-major; std[sampled mode] is not used
+ *          (may be NULL);
+ *   perm:  device [count x R] int32 or NULL: perm[j*R + s] is the component
+ *          of model first+j matched to reference component s;
+ *   sign:  device [N x count x R] or NULL: sign[(n*count + j)*R + s] = +1 or
+ *          -1, the sign applied to that matched column in mode n (+1 for the
+ *          sampled mode and for zero columns).
+ * Matching (a reading; the paper defers to its citation): congruence of a
+ * submodel component with a reference component = product over the
+ * non-sampled modes of the cosines of their loading vectors; the assignment
+ * maximising the sum of absolute congruences is solved exactly.  Scale
+ * adjustment: non-sampled loading vectors scaled to unit norm, sign chosen
+ * so the inner product with the matched reference vector is >= 0.
+ * Deviation: S = sqrt((count-1)/count * sum_j (theta_j - mean)^2).
+ * JKC_EINVAL for an out-of-range ref or set, a rank mismatch or a missing
+ * std[n].  Asynchronous; the context's workspace holds the matching. */
+jkc_status jk_cals_jackknife_std(jkc_ctx *ctx, int32_t ref, int32_t first, int32_t count,
+                                 double *const *std, int32_t *perm, double *sign);
+
 /* Time each candidate MTTKRP tiling of every mode on this problem and keep
  * the fastest (restores the factors it started with).  Synchronous.
  * Optional: a context works with its built-in choice without it. */

@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
         "jk_cals_profile": (I32, [VP, I32]),
         "jk_cals_profile_read": (I32, [VP, VP, VP]),
         "jk_cals_set_tiling": (I32, [VP, I32, I32, I32]),
+        "jk_cals_jackknife_std": (I32, [VP, I32, I32, I32, P(VP), VP, VP]),
         "jk_cals_remove_slice": (I32, [P(Problem), VP, I32, VP]),
         "jk_cals_destroy": (None, [VP]),
         "jk_cals_last_error": (ctypes.c_char_p, []),
@@ -288,6 +289,24 @@ class JkCals:
     def tune(self, reps: int = 3):
         _check(lib().jk_cals_tune(self.ctx, int(reps)))
 
+    def jackknife_std(self, ref: int, first: int, count: int, with_matching: bool = False):
+        """Alg. 2's jackknife standard deviations of the models first ..
+        first+count-1 against model ``ref``: {mode: I_n x R tensor} for
+        every mode except the sampled one; with_matching also returns the
+        matched components (count x R int32) and signs (N x count x R)."""
+        import torch
+        R = int(self.ranks[ref])
+        out = {n: torch.empty((self.dims[n], R), dtype=torch.float64, device="cuda")
+               for n in range(self.N) if n != self.sampled_mode}
+        ptrs = (ctypes.c_void_p * self.N)(*[_ptr(out.get(n)) for n in range(self.N)])
+        perm = sign = None
+        if with_matching:
+            perm = torch.empty((count, R), dtype=torch.int32, device="cuda")
+            sign = torch.empty((self.N, count, R), dtype=torch.float64, device="cuda")
+        _check(lib().jk_cals_jackknife_std(self.ctx, int(ref), int(first), int(count), ptrs,
+                                           ctypes.c_void_p(_ptr(perm)), ctypes.c_void_p(_ptr(sign))))
+        return (out, perm, sign) if with_matching else out
+
     def describe(self, mode: int) -> str:
         return lib().jk_cals_describe(self.ctx, int(mode)).decode()
 
@@ -358,6 +377,10 @@ def jk_cals_refine(ctx: JkCals, steps: int, loss=None):
 
 def jk_cals_tune(ctx: JkCals, reps: int = 3):
     return ctx.tune(reps)
+
+
+def jk_cals_jackknife_std(ctx: JkCals, ref: int, first: int, count: int, with_matching=False):
+    return ctx.jackknife_std(ref, first, count, with_matching)
 
 
 def jk_cals_describe(ctx: JkCals, mode: int) -> str:

@@ -112,6 +112,9 @@ struct Plan {
     items.push_back({"upart", update_rows_scratch(maxI, gsize, K) * 8});
     // split paths: float32 copies of the factors, refreshed before each MTTKRP
     for (int n = 0; n < N; ++n) items.push_back({"Uf", precision != JKC_FP64 ? dims[n] * ldc * 4 : 0});
+    // jackknife post-processing: matched components and signed inverse norms
+    items.push_back({"jk_perm", (int64_t)ldc * 4});
+    items.push_back({"jk_scale", (int64_t)N * ldc * 8});
     total = 0;
     for (auto& it : items) total += align_up(std::max<int64_t>(it.bytes, 1), kAlign);
   }
@@ -766,6 +769,8 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
   c.counter = static_cast<int32_t*>(take(it++));
   c.upart = static_cast<double*>(take(it++));
   for (int n = 0; n < pl.N; ++n) c.Uf[n] = static_cast<float*>(take(it++));
+  c.jk_perm = static_cast<int32_t*>(take(it++));
+  c.jk_scale = static_cast<double*>(take(it++));
 
   hipStream_t st = c.stream;
   // model tables (host vectors live in the context, so the copies are safe)
@@ -955,6 +960,45 @@ jkc_status jk_cals_refine(jkc_ctx* ctx, int32_t steps, double* loss) {
     for (int n = 0; n < ctx->N; ++n) JKC_TRY(enqueue_gram(ctx, n));
   }
   if (loss) JKC_TRY(enqueue_loss_grad(ctx, loss));
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_jackknife_std(jkc_ctx* ctx, int32_t ref, int32_t first, int32_t count,
+                                 double* const* std_out, int32_t* perm, double* sign) {
+  JKC_TRY(check_ctx(ctx));
+  if (ref < 0 || ref >= ctx->K) return fail(JKC_EINVAL, "ref out of range");
+  if (count < 1 || first < 0 || first > ctx->K - count)
+    return fail(JKC_EINVAL, "models first .. first+count-1 out of range");
+  if (!std_out) return fail(JKC_EINVAL, "std is NULL");
+  const int R = ctx->h_rank[ref];
+  for (int k = first; k < first + count; ++k)
+    if (ctx->h_rank[k] != R)
+      return fail(JKC_EINVAL, "model " + std::to_string(k) + " has another rank than the reference");
+  for (int n = 0; n < ctx->N; ++n)
+    if (n != ctx->nhat && !std_out[n]) return fail(JKC_EINVAL, "std[n] is NULL for a non-sampled mode");
+  JkArgs a{};
+  a.N = ctx->N;
+  a.nhat = ctx->nhat;
+  a.R = R;
+  a.ref_off = ctx->h_off[ref];
+  a.first_off = ctx->h_off[first];
+  a.count = count;
+  a.ldc = ctx->ldc;
+  for (int n = 0; n < kMaxOrder; ++n) {
+    a.dims[n] = n < ctx->N ? (int32_t)ctx->dims[n] : 0;
+    a.U[n] = n < ctx->N ? ctx->U[n] : nullptr;
+    a.std_out[n] = n < ctx->N && n != ctx->nhat ? std_out[n] : nullptr;
+  }
+  a.perm = ctx->jk_perm;
+  a.scale = ctx->jk_scale;
+  JKC_HIP(launch_jk(a, ctx->stream));
+  if (perm)
+    JKC_HIP(hipMemcpyAsync(perm, ctx->jk_perm + a.first_off, (size_t)count * R * 4,
+                           hipMemcpyDeviceToDevice, ctx->stream));
+  if (sign)
+    JKC_HIP(launch_jk_signs(ctx->jk_scale, ctx->ldc, ctx->N, a.first_off, count * R, sign,
+                            ctx->stream));
   g_last_error.clear();
   return JKC_OK;
 }

@@ -108,6 +108,25 @@ struct UpdateArgs {
   int32_t nch;                    // row-parallel update: chunks per model
 };
 
+// Jackknife post-processing of a set of `count` models of rank R with
+// contiguous columns (model j of the set at first_off + j * R).
+struct JkArgs {
+  int32_t N, nhat;
+  int32_t R;
+  int32_t ref_off;            // first column of the reference model
+  int32_t first_off;          // first column of the set
+  int32_t count;
+  int32_t ldc;
+  int32_t dims[kMaxOrder];
+  const double* U[kMaxOrder];
+  int32_t* perm;              // [ldc]: at column first_off + j*R + s, the component of model j matched to s
+  double* scale;              // [N][ldc]: signed inverse norms of the matched columns (0 for the sampled mode)
+  double* std_out[kMaxOrder]; // I_n x R row-major; unused for the sampled mode
+};
+hipError_t launch_jk(const JkArgs& a, hipStream_t s);
+hipError_t launch_jk_signs(const double* scale, int32_t ldc, int32_t N, int32_t first_off,
+                           int32_t cols, double* sign, hipStream_t s);
+
 // Rows per block of the row-parallel update, and its scratch (doubles).
 constexpr int kUpdRows = 64;
 inline int64_t update_rows_scratch(int64_t maxI, int64_t gsize, int64_t K) {
@@ -242,6 +261,8 @@ struct jkc_ctx {
   bool lambda_is_one = true;     // lambda folded into the last factor
   int update_kernel = 0;         // 0 LDS-staged, 1 global, 2 row-parallel
   double* upart = nullptr;       // row-parallel update scratch
+  int32_t* jk_perm = nullptr;     // jackknife matching: [ldc]
+  double* jk_scale = nullptr;     // jackknife matching: [N][ldc]
   bool use_graph = true;         // replay sweeps from a captured HIP graph
   hipGraphExec_t graph_exec = nullptr;
 

@@ -115,6 +115,8 @@ def test_null_context_rejected(L):
     assert L.jk_cals_set_sweep_graph(None, 1) == jk.JKC_EINVAL
     assert L.jk_cals_profile(None, 1) == jk.JKC_EINVAL
     assert L.jk_cals_profile_read(None, None, None) == jk.JKC_EINVAL
+    stds = (ctypes.c_void_p * 3)(0x1000, 0x1000, 0x1000)
+    assert L.jk_cals_jackknife_std(None, 0, 1, 1, stds, None, None) == jk.JKC_EINVAL
     assert L.jk_cals_num_tilings(None) == 0
     assert L.jk_cals_describe(None, 0) == b""
     L.jk_cals_destroy(None)
