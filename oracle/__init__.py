@@ -50,7 +50,7 @@ it to the paper and to mathematics live in ``tests/test_oracle_*.py``.
 from .cp import (unfold, khatri_rao, krp_excluding, mttkrp, mttkrp_bruteforce,
                  gram, hadamard_of_grams, solve_normal, normalise_columns,
                  error_fast, reconstruct, residual_explicit)
-from .jackknife import (reduce_tensor, reduce_init, cp_als, jk_als, loss, grad,
+from .jackknife import (reduce_tensor, reduce_init, left_out_rows, cp_als, jk_als, loss, grad,
                         loss_and_grad, fd_grad, gd_refine, flops_jk_als,
                         flops_jk_cals, flop_ratio, model_offsets, ModelResult)
 from .postprocess import congruence, match_components, aligned_factors, jackknife_std
@@ -59,7 +59,7 @@ __all__ = [
     "unfold", "khatri_rao", "krp_excluding", "mttkrp", "mttkrp_bruteforce",
     "gram", "hadamard_of_grams", "solve_normal", "normalise_columns",
     "error_fast", "reconstruct", "residual_explicit", "reduce_tensor",
-    "reduce_init", "cp_als", "jk_als", "loss", "grad", "loss_and_grad", "fd_grad",
+    "reduce_init", "left_out_rows", "cp_als", "jk_als", "loss", "grad", "loss_and_grad", "fd_grad",
     "gd_refine", "flops_jk_als", "flops_jk_cals", "flop_ratio", "model_offsets",
     "ModelResult", "congruence", "match_components", "aligned_factors", "jackknife_std",
 ]

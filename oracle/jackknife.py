@@ -22,7 +22,7 @@ class ModelResult:
     """Outcome of one submodel fit.  Factors are stored reduced (row p of the
     sampled mode absent) unless produced by ``padded``."""
 
-    left_out: int
+    left_out: object        # -1, one index, or a tuple of d indices (delete-d)
     sampled_mode: int
     U: List[np.ndarray]
     lam: np.ndarray
@@ -38,35 +38,50 @@ class ModelResult:
     M_last: Optional[np.ndarray] = None
 
     def padded(self, U: Optional[Sequence[np.ndarray]] = None) -> List[np.ndarray]:
-        """Factors with a zero row re-inserted at the left-out index of the
+        """Factors with zero rows re-inserted at the left-out indices of the
         sampled mode, matching the zero-padded multi-factor of Alg. 3."""
         U = self.U if U is None else U
         out = [u.copy() for u in U]
-        if self.left_out >= 0:
+        rows = left_out_rows(self.left_out)
+        if rows:
             n = self.sampled_mode
-            out[n] = np.insert(out[n], self.left_out, 0.0, axis=0)
+            I = out[n].shape[0] + len(rows)
+            full = np.zeros((I, out[n].shape[1]))
+            full[np.setdiff1d(np.arange(I), rows)] = out[n]
+            out[n] = full
         return out
 
 
-def reduce_tensor(T: np.ndarray, sampled_mode: int, p: int) -> np.ndarray:
-    """T_{-p}: T with slice p of the sampled mode deleted (Alg. 2, slice
-    removal); the full tensor when p = -1."""
+def left_out_rows(p) -> List[int]:
+    """The samples a model leaves out: none for -1 (or a list of -1), one
+    for an index, d for a list of d indices (delete-d jackknife)."""
+    rows = [int(x) for x in np.atleast_1d(np.asarray(p)).ravel()]
+    return sorted(x for x in rows if x >= 0)
+
+
+def reduce_tensor(T: np.ndarray, sampled_mode: int, p) -> np.ndarray:
+    """T_{-P}: T with the slices P of the sampled mode deleted (Alg. 2,
+    slice removal; d slices for delete-d); the full tensor when P is empty
+    (p = -1)."""
     T = np.asarray(T, dtype=np.float64)
-    if p < 0:
+    rows = left_out_rows(p)
+    if not rows:
         return T
-    return np.delete(T, p, axis=sampled_mode)
+    return np.delete(T, rows, axis=sampled_mode)
 
 
-def reduce_init(U_init: np.ndarray, p: int) -> np.ndarray:
-    """The sampled mode's factor with row p deleted (Alg. 2, row removal)."""
-    if p < 0:
+def reduce_init(U_init: np.ndarray, p) -> np.ndarray:
+    """The sampled mode's factor with the rows P deleted (Alg. 2, row
+    removal)."""
+    rows = left_out_rows(p)
+    if not rows:
         return np.array(U_init, dtype=np.float64)
-    return np.delete(np.asarray(U_init, dtype=np.float64), p, axis=0)
+    return np.delete(np.asarray(U_init, dtype=np.float64), rows, axis=0)
 
 
 def cp_als(T: np.ndarray, U0: Sequence[np.ndarray], sweeps: int, tol: float = 0.0,
            record_factors: Sequence[int] = (), sampled_mode: int = 0,
-           left_out: int = -1) -> ModelResult:
+           left_out=-1) -> ModelResult:
     """CP-ALS (Alg. 1) on tensor T from factors U0, in float64.
 
     One sweep updates modes 0..N-1 in order; each update is MTTKRP, the
@@ -128,8 +143,10 @@ def jk_als(T: np.ndarray, sampled_mode: int, ranks: Sequence[int],
     """Jackknife by independent submodel fits (the fitting loop of Alg. 2).
 
     Model k takes columns [off_k, off_k + ranks[k]) of every initial
-    multi-factor ``init[n]`` (I_n x C), deletes row left_out[k] of the
-    sampled mode's block and slice left_out[k] of T, and runs ``cp_als``.
+    multi-factor ``init[n]`` (I_n x C), deletes row(s) left_out[k] of the
+    sampled mode's block and the same slice(s) of T, and runs ``cp_als``.
+    left_out[k] is one index (or -1) for leave-one-out, or a list of d
+    indices for delete-d jackknife (Sec. 4.1, closing remark).
     ``models`` restricts the run to a subset (the results of the others are
     unaffected, since submodels never interact).
     """
@@ -138,7 +155,8 @@ def jk_als(T: np.ndarray, sampled_mode: int, ranks: Sequence[int],
     out = {}
     for k in todo:
         k = int(k)
-        p = int(left_out[k])
+        p = left_out[k]
+        p = int(p) if np.ndim(p) == 0 else tuple(int(x) for x in p)
         cols = slice(int(off[k]), int(off[k] + ranks[k]))
         U0 = [np.array(init[n][:, cols], dtype=np.float64) for n in range(len(init))]
         U0[sampled_mode] = reduce_init(U0[sampled_mode], p)

@@ -11,12 +11,14 @@ Layout conventions shared by every consumer:
   order, so ``T.ravel(order="F")`` is the column-major, i_1-fastest storage
   of Eq. (3) (element (i_1, ..., i_N) at offset i_1 + I_1*(i_2 + I_2*(...)));
 * a model table is two int32 arrays ``ranks[K]`` and ``left_out[K]``
-  (``-1`` marks a full model that keeps every sample); model k owns the
+  (``-1`` marks a full model that keeps every sample), or ``left_out[K, d]``
+  for delete-d jackknife (row k lists the d samples model k leaves out, a row
+  of ``-1`` a full model); model k owns the
   columns ``[off_k, off_k + ranks[k])`` of every multi-factor, with offsets
   taken in model order;
 * an initial multi-factor for mode n is an ``I_n x C`` float64 array in C
   order (C contiguous), with C = sum(ranks).  It is *not* pre-zeroed: the
-  consumer removes (oracle) or zeroes (GPU path) row ``left_out[k]`` of the
+  consumer removes (oracle) or zeroes (GPU path) the left-out rows of the
   sampled mode itself.
 
 Random streams: ``SeedSequence(211203985 + config_index).spawn(3)`` gives the
@@ -40,7 +42,7 @@ class Workload:
     T: np.ndarray                 # Fortran-ordered tensor (I_1, ..., I_N)
     sampled_mode: int             # the paper's n-hat, 0-based
     ranks: np.ndarray             # int32 [K]
-    left_out: np.ndarray          # int32 [K], -1 = full model
+    left_out: np.ndarray          # int32 [K] or [K, d] (delete-d), -1 = full model
     init: List[np.ndarray]        # per mode, I_n x C float64, C-contiguous
     sweeps: int                   # iteration budget of the configuration
     truth: Optional[List[np.ndarray]] = None   # generating factors (for pins)
@@ -103,6 +105,17 @@ def loo_table(I: int, R: int, include_full: bool = False):
     return ranks, np.asarray(lo, dtype=np.int32)
 
 
+def delete_d_table(I: int, d: int, R: int, include_full: bool = False):
+    """Delete-d jackknife over I samples in groups of d consecutive samples
+    (the last group smaller when d does not divide I is dropped), all models
+    of rank R: left_out is [K, d] (full model first, as a row of -1)."""
+    groups = [list(range(g * d, g * d + d)) for g in range(I // d)]
+    if include_full:
+        groups = [[-1] * d] + groups
+    ranks = np.full(len(groups), R, dtype=np.int32)
+    return ranks, np.asarray(groups, dtype=np.int32).reshape(len(groups), d)
+
+
 def shared_parent_init(rng: np.random.Generator, dims, parents_R: Sequence[int],
                        children: Sequence[int]):
     """One N(0,1) parent init per entry of ``parents_R``; parent q is repeated
@@ -144,20 +157,22 @@ def config1() -> Workload:
     return Workload("c1_20x30x40_r3_loo+full", T, 0, ranks, lo, init, 50, A)
 
 
-def config2(dims=(100, 200, 200), models: Optional[int] = None) -> Workload:
+def config2(dims=(100, 200, 200), models: Optional[int] = None, delete_d: int = 1) -> Workload:
     """Fluorescence-like 3-way tensor: mode 1 concentrations U(0,1), modes 2
     and 3 Gaussian-peak spectra; rank 5, 2 % noise; leave-one-out over all
-    mode-1 samples at rank 5 from a shared N(0,1) parent init; 100 sweeps."""
+    mode-1 samples at rank 5 from a shared N(0,1) parent init; 100 sweeps.
+    delete_d > 1: delete-d jackknife over groups of d consecutive samples
+    instead (I / d submodels), the same tensor and init."""
     rf, rn, ri = streams(2)
     R0 = 5
     A = [rf.uniform(0.0, 1.0, size=(dims[0], R0))]
     A += [gaussian_peaks(rf, I, R0) for I in dims[1:]]
     T = add_noise(dense_from_factors(A), rn, 0.02)
-    ranks, lo = loo_table(dims[0], 5)
+    ranks, lo = loo_table(dims[0], 5) if delete_d <= 1 else delete_d_table(dims[0], delete_d, 5)
     if models is not None:
         ranks, lo = ranks[:models], lo[:models]
     init = shared_parent_init(ri, dims, [5], [len(ranks)])
-    name = "c2_%dx%dx%d_r5_loo" % tuple(dims)
+    name = "c2_%dx%dx%d_r5_%s" % (tuple(dims) + ("loo" if delete_d <= 1 else "delete%d" % delete_d,))
     return Workload(name, T, 0, ranks, lo, init, 100, A)
 
 

@@ -38,13 +38,16 @@ def oracle_model_mttkrp(wl, k, n, factors=None):
     src = wl.init if factors is None else factors
     c = cols(wl, k)
     U = [np.array(src[m][:, c], dtype=np.float64) for m in range(len(wl.dims))]
-    p = int(wl.left_out[k])
+    p = wl.left_out[k]
+    rows = oracle.left_out_rows(p)
     nh = wl.sampled_mode
     U[nh] = oracle.reduce_init(U[nh], p)
     Tk = oracle.reduce_tensor(np.asarray(wl.T, dtype=np.float64), nh, p)
     M = oracle.mttkrp(Tk, U, n)
-    if n == nh and p >= 0:
-        M = np.insert(M, p, 0.0, axis=0)
+    if n == nh and rows:
+        full = np.zeros((wl.dims[nh], M.shape[1]))
+        full[np.setdiff1d(np.arange(wl.dims[nh]), rows)] = M
+        M = full
     return M
 
 
