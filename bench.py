@@ -48,6 +48,9 @@ def parse():
                     help="c2: the benchmark workload (default); c3/c4: the uneven-batch and "
                          "split-precision workloads, for kernel measurements")
     ap.add_argument("--precision", default=None, choices=["fp64", "bf16x3", "bf16x6"])
+    ap.add_argument("--delete-d", type=int, default=1,
+                    help="c2 only: delete-d jackknife over groups of d consecutive samples "
+                         "(I/d submodels; the baselines are skipped)")
     ap.add_argument("--efficiency-sweep", action="store_true",
                     help="instead of the benchmark: fused MTTKRP efficiency against the column "
                          "count C on a 50x200x200 tensor (the analogue of the paper's Fig. 1); "
@@ -135,7 +138,14 @@ def main():
     torch.cuda.set_device(0)
     if args.efficiency_sweep:
         return efficiency_sweep()
-    if args.workload == "c2":
+    if args.workload == "c2" and args.delete_d > 1:
+        wl = synth.config2(delete_d=args.delete_d)
+        desc_w = ("c2: 100x200x200 f64 fluorescence-like tensor, rank 5, 2%%%% noise; "
+                  "%d delete-%d submodels of rank 5; %%d ALS sweeps" % (wl.K, args.delete_d))
+        prec_name = args.precision or "fp64"
+        args.no_plain = True
+        args.no_cpu = True
+    elif args.workload == "c2":
         wl = synth.config2()
         desc_w = ("c2: 100x200x200 f64 fluorescence-like tensor, rank 5, 2%% noise; "
                   "100 leave-one-out submodels of rank 5; %d ALS sweeps")
@@ -236,11 +246,13 @@ def main():
     # standard deviations) of one set of fitted submodels: the leave-one-out
     # run after the first model, against the full model when there is one
     # (else against the first submodel), at most one per left-out sample
+    def first_left(k):
+        return int(np.asarray(wl.left_out[k]).ravel()[0])
     ref = 0
-    s0 = 1 if int(wl.left_out[0]) < 0 and K > 1 else 0
+    s0 = 1 if first_left(0) < 0 and K > 1 else 0
     cnt = 0
     while (s0 + cnt < K and cnt < wl.dims[0] and int(wl.ranks[s0 + cnt]) == int(wl.ranks[ref])
-           and int(wl.left_out[s0 + cnt]) >= 0):
+           and first_left(s0 + cnt) >= 0):
         cnt += 1
     jk_ms = None
     if cnt > 0:
@@ -286,6 +298,9 @@ def main():
            "data": "synthetic",
            "config": {"workload": desc_w % sweeps, "dims": list(wl.dims), "models": K,
                       "columns": C, "sweeps": sweeps, "precision": prec_name,
+                      "delete_d": int(wl.left_out.shape[1]) if wl.left_out.ndim == 2 else 1,
+                      "fused_flop_overhead": round(wl.dims[0] / (wl.dims[0] - (
+                          int(wl.left_out.shape[1]) if wl.left_out.ndim == 2 else 1)), 5),
                       "tiling": tiling or desc},
            "mttkrp_tflops": round(achieved, 3),
            "roofline": roofline,

@@ -11,7 +11,8 @@
  * products (Alg. 3, MTTKRP step).  A submodel that leaves out sample p of
  * the sampled mode keeps a row of zeros at index p of that mode's factor
  * (Case II), and the fused MTTKRP's row p is discarded for that model when
- * the sampled mode itself is updated (Case I).
+ * the sampled mode itself is updated (Case I).  Delete-d jackknife keeps d
+ * such rows per submodel (Sec. 4.1, closing remark).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -19,7 +20,10 @@
  *   with i_1 fastest (Eq. (3)): element (i_1..i_N) at offset
  *   i_1 + I_1*(i_2 + I_2*(i_3 + ...)).  float64 or float32 (tensor_dtype).
  * Models: K models; model k has rank R_k (1..JKC_MAX_RANK) and leaves out
- *   sample left_out[k] of the sampled mode (-1: full model, keeps all).
+ *   the samples P_k of the sampled mode listed in left_out (one per model,
+ *   or d per model with delete_d = d; -1: full model, keeps all).
+ *   "The left-out rows of model k" below are the rows P_k of the sampled
+ *   mode in model k's columns.
  *   Model k owns columns [off_k, off_k + R_k) with off_k = R_0+...+R_{k-1}.
  *   C = R_0 + ... + R_{K-1}.
  * Factors, MTTKRP results and gradients: device float64, row-major
@@ -92,12 +96,21 @@ typedef struct {
   int32_t sampled_mode;        /* n-hat, 0-based, in [0, N)                   */
   int32_t num_models;          /* K >= 1                                      */
   const int32_t *ranks;        /* host [K], 1..JKC_MAX_RANK                    */
-  const int32_t *left_out;     /* host [K], -1 or in [0, dims[sampled_mode]) */
+  const int32_t *left_out;     /* host [K x d] row-major, d = max(1,
+                                  delete_d): model k leaves out the samples
+                                  left_out[k*d .. k*d+d-1] of the sampled
+                                  mode, all distinct and in
+                                  [0, dims[sampled_mode]), or all -1 (a model
+                                  fitted to all of T)                        */
   int32_t tensor_dtype;        /* jkc_tensor_dtype                            */
   int32_t precision;           /* jkc_precision                               */
   int32_t copy_tensor;         /* 1: copy T into the workspace; 0: use in place
                                   (JKC_FP64 only)                             */
   void *stream;                /* hipStream_t, NULL = default stream          */
+  int32_t delete_d;            /* samples left out per submodel: 0 or 1 =
+                                  leave-one-out, d > 1 = delete-d jackknife
+                                  (Sec. 4.1: d zero rows padded and kept zero
+                                  instead of one); d < dims[sampled_mode]   */
 } jkc_problem;
 
 /* Bytes of device workspace the problem needs.  Host only, no device work. */
@@ -106,29 +119,29 @@ jkc_status jk_cals_workspace_size(const jkc_problem *prob, size_t *bytes);
 /* Create a context (Alg. 3, initialisation of the multi-factors).
  *   tensor : device, layout above.
  *   init   : host array [N] of device pointers; init[n] is I_n x C float64,
- *            row-major.  Row left_out[k] of model k's block in the sampled
- *            mode is zeroed by the library (the inserted zero row), so the
+ *            row-major.  The left-out rows of model k's block in the sampled
+ *            mode are zeroed by the library (the inserted zero rows), so the
  *            caller may pass an unzeroed parent initialisation.
  *   workspace : device, >= jk_cals_workspace_size bytes, 256-byte aligned.
  *   out    : receives the context.  Owned by the caller; free with
  *            jk_cals_destroy.
  * Enqueues the tensor copy (or bfloat16 split), the slice norms
- * ||T_{-p}||^2 used by the submodel error (Alg. 3, error step), factor
+ * ||T_{-P_k}||^2 used by the submodel error (Alg. 3, error step), factor
  * packing and the initial Gram matrices.  Asynchronous on the stream. */
 jkc_status jk_cals_init(const jkc_problem *prob, const void *tensor,
                         const double *const *init, void *workspace,
                         size_t ws_bytes, jkc_ctx **out);
 
 /* The fused MTTKRP of Alg. 3 for one mode, at the context's current factors:
- * out = T_(mode) (multi-factor Khatri-Rao product), with row left_out[k] of
- * model k's columns set to 0 when mode == sampled_mode (Case I).
+ * out = T_(mode) (multi-factor Khatri-Rao product), with the left-out rows
+ * of model k's columns set to 0 when mode == sampled_mode (Case I).
  *   out : device, I_mode x C float64, row-major.  Asynchronous. */
 jkc_status jk_cals_mttkrp(jkc_ctx *ctx, int32_t mode, double *out);
 
 /* Run nsweeps full ALS sweeps (Alg. 3, one pass of the repeat loop each) for
  * every model that is not frozen, with no convergence test (the fixed
  * iteration protocol of Sec. 5.1).  After the last sweep, if fit != NULL,
- * fit[k] (device [K] float64) receives 1 - ||T_{-p} - model|| / ||T_{-p}||.
+ * fit[k] (device [K] float64) receives 1 - ||T_{-P_k} - model|| / ||T_{-P_k}||.
  * Asynchronous. */
 jkc_status jk_cals_sweep(jkc_ctx *ctx, int32_t nsweeps, double *fit);
 
@@ -147,7 +160,7 @@ jkc_status jk_cals_get_factors(jkc_ctx *ctx, int32_t mode, double *out,
                                double *lambda);
 
 /* Replace the factor of `mode` (device I_mode x C) and, if lambda != NULL,
- * lambda (device [C]); row left_out[k] of the sampled mode is re-zeroed and
+ * lambda (device [C]); the left-out rows of the sampled mode are re-zeroed and
  * the mode's Gram matrices are recomputed.  Asynchronous. */
 jkc_status jk_cals_set_factors(jkc_ctx *ctx, int32_t mode, const double *in,
                                const double *lambda);
@@ -157,11 +170,11 @@ jkc_status jk_cals_set_factors(jkc_ctx *ctx, int32_t mode, const double *in,
 jkc_status jk_cals_get_status(jkc_ctx *ctx, double *err, double *fit,
                               int32_t *status, int32_t *iters);
 
-/* Least-squares CP loss f_k = 1/2 ||T_{-p_k} - [[U^(k)]]||^2 per model for
+/* Least-squares CP loss f_k = 1/2 ||T_{-P_k} - [[U^(k)]]||^2 per model for
  * the context's factors with lambda folded into the last mode (the
  * all-at-once formulation the paper cites in Sec. 2), and its gradient
  * dF/dU_n = U_n H_n - M_n for every mode (an all-mode fused MTTKRP), with
- * row left_out[k] of the sampled mode held at 0.  lambda is folded into the
+ * the left-out rows of the sampled mode held at 0.  lambda is folded into the
  * last factor first (and reset to 1).  loss: device [K] (may be NULL).  The
  * gradients stay in the workspace for jk_cals_get_grad.  Asynchronous. */
 jkc_status jk_cals_loss_grad(jkc_ctx *ctx, double *loss);

@@ -54,6 +54,7 @@ class Problem(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("copy_tensor", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
+        ("delete_d", ctypes.c_int32),
     ]
 
 
@@ -140,12 +141,16 @@ def to_device_tensor(T: np.ndarray, device="cuda"):
 def make_problem(dims, sampled_mode, ranks, left_out, tensor_dtype=JKC_TENSOR_F64,
                  precision=JKC_FP64, copy_tensor=1, stream=0):
     """Build the C problem descriptor; the returned tuple keeps the host
-    arrays alive."""
+    arrays alive.  left_out is [K] (leave-one-out) or [K, d] (delete-d:
+    row k lists the d samples model k leaves out, or d times -1)."""
     d = (ctypes.c_int64 * len(dims))(*[int(x) for x in dims])
     r = (ctypes.c_int32 * len(ranks))(*[int(x) for x in ranks])
-    lo = (ctypes.c_int32 * len(left_out))(*[int(x) for x in left_out])
+    lo_np = np.asarray(left_out, dtype=np.int64)
+    del_d = int(lo_np.shape[1]) if lo_np.ndim == 2 else 1
+    flat = lo_np.reshape(-1)
+    lo = (ctypes.c_int32 * len(flat))(*[int(x) for x in flat])
     prob = Problem(len(dims), d, int(sampled_mode), len(ranks), r, lo, int(tensor_dtype),
-                   int(precision), int(copy_tensor), ctypes.c_void_p(stream))
+                   int(precision), int(copy_tensor), ctypes.c_void_p(stream), del_d)
     return prob, (d, r, lo)
 
 

@@ -61,6 +61,7 @@ struct Plan {
   int64_t strides[kMaxOrder] = {0, 0, 0, 0};
   int64_t P = 0, maxI = 0, gsize = 0;
   int tensor_f32 = 0, precision = 0, copy_tensor = 1;
+  int del_d = 1;   // rows of the sampled mode left out per submodel
   int split_max[kMaxOrder] = {1, 1, 1, 1};
   int64_t partial_doubles = 0;
 
@@ -101,10 +102,9 @@ struct Plan {
     items.push_back({"iters", (int64_t)K * 4});
     items.push_back({"off", (int64_t)K * 4});
     items.push_back({"rank", (int64_t)K * 4});
-    items.push_back({"left", (int64_t)K * 4});
+    items.push_back({"lomask", dims[nhat] * (int64_t)K});
     items.push_back({"order", (int64_t)K * 4});
     items.push_back({"goff", (int64_t)K * 8});
-    items.push_back({"colp", (int64_t)ldc * 4});
     items.push_back({"colmodel", (int64_t)ldc * 4});
     items.push_back({"slice", dims[nhat] * 8});
     items.push_back({"slice_part", (int64_t)kSliceChunks * dims[nhat] * 8});
@@ -160,12 +160,27 @@ jkc_status make_plan(const jkc_problem* prob, Plan* pl) {
   pl->K = prob->num_models;
   int64_t C = 0, gsize = 0;
   const int64_t Ih = pl->dims[pl->nhat];
+  if (prob->delete_d < 0) return fail(JKC_EINVAL, "delete_d must be >= 0");
+  const int d = prob->delete_d > 1 ? prob->delete_d : 1;
+  if (d > 1 && d >= Ih) return fail(JKC_EINVAL, "delete_d must leave at least one sample");
+  pl->del_d = d;
+  std::vector<int64_t> seen(Ih, -1);
   for (int k = 0; k < pl->K; ++k) {
     const int R = prob->ranks[k];
     if (R < 1 || R > kMaxRank) return fail(JKC_EINVAL, "rank must be in 1..32 (model " + std::to_string(k) + ")");
-    const int p = prob->left_out[k];
-    if (p < -1 || p >= Ih) return fail(JKC_EINVAL, "left_out out of range (model " + std::to_string(k) + ")");
-    if (p >= 0 && Ih < 2) return fail(JKC_EINVAL, "cannot leave out the only sample");
+    const int32_t* rows = prob->left_out + (int64_t)k * d;
+    const bool full = rows[0] == -1;
+    for (int j = 0; j < d; ++j) {
+      const int p = rows[j];
+      const std::string mk = " (model " + std::to_string(k) + ")";
+      if (p < -1 || p >= Ih) return fail(JKC_EINVAL, "left_out out of range" + mk);
+      if ((p == -1) != full) return fail(JKC_EINVAL, "left_out mixes -1 and sample indices" + mk);
+      if (p >= 0 && Ih < 2) return fail(JKC_EINVAL, "cannot leave out the only sample");
+      if (p >= 0) {
+        if (seen[p] == k) return fail(JKC_EINVAL, "left_out repeats a sample" + mk);
+        seen[p] = k;
+      }
+    }
     C += R;
     gsize += (int64_t)R * R;
   }
@@ -480,7 +495,7 @@ jkc_status enqueue_mttkrp_reduced(jkc_ctx* ctx, int n, double* out, int ldo, int
   const int splits = effective_splits(ctx, n, t);
   const double* src = splits > 1 ? ctx->partial : ctx->Mbuf;
   if (splits == 1 && out == ctx->Mbuf) return JKC_OK;  // rows cleared by the consumer
-  JKC_HIP(launch_reduce(src, splits, (int32_t)ctx->dims[n], ctx->ldc, ncols, ctx->d_colp,
+  JKC_HIP(launch_reduce(src, splits, (int32_t)ctx->dims[n], ctx->ldc, ncols, ctx->left_out(),
                         n == ctx->nhat ? 1 : 0, out, ldo, ctx->stream));
   return JKC_OK;
 }
@@ -623,7 +638,7 @@ jkc_status enqueue_loss_grad(jkc_ctx* ctx, double* loss) {
     JKC_TRY(enqueue_mttkrp_reduced(ctx, n, ctx->Mbuf, ctx->ldc, ctx->ldc));
     if (effective_splits(ctx, n, ctx->tiling[n]) == 1 && n == ctx->nhat) {
       // the direct product still carries row p: clear it through a reduce pass
-      JKC_HIP(launch_reduce(ctx->Mbuf, 1, (int32_t)ctx->dims[n], ctx->ldc, ctx->ldc, ctx->d_colp,
+      JKC_HIP(launch_reduce(ctx->Mbuf, 1, (int32_t)ctx->dims[n], ctx->ldc, ctx->ldc, ctx->left_out(),
                             1, ctx->Mbuf, ctx->ldc, ctx->stream));
     }
     GradArgs g{};
@@ -711,20 +726,24 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
   c.rmax = 0;
   for (int k = 0; k < pl.K; ++k) c.rmax = std::max(c.rmax, prob->ranks[k]);
   c.h_rank.assign(prob->ranks, prob->ranks + pl.K);
-  c.h_left.assign(prob->left_out, prob->left_out + pl.K);
+  c.del_d = pl.del_d;
+  c.h_left.resize(pl.K);
+  c.h_lomask.assign(pl.dims[pl.nhat] * pl.K, 0);
+  for (int k = 0; k < pl.K; ++k) {
+    const int32_t* rows = prob->left_out + (int64_t)k * pl.del_d;
+    c.h_left[k] = rows[0];
+    for (int j = 0; j < pl.del_d; ++j)
+      if (rows[j] >= 0) c.h_lomask[(int64_t)rows[j] * pl.K + k] = 1;
+  }
   c.h_off.resize(pl.K);
   c.h_goff.resize(pl.K);
-  c.h_colp.assign(pl.ldc, -1);
-  c.h_colmodel.assign(pl.ldc, 0);
+  c.h_colmodel.assign(pl.ldc, -1);
   int32_t off = 0;
   int64_t goff = 0;
   for (int k = 0; k < pl.K; ++k) {
     c.h_off[k] = off;
     c.h_goff[k] = goff;
-    for (int r = 0; r < c.h_rank[k]; ++r) {
-      c.h_colp[off + r] = c.h_left[k];
-      c.h_colmodel[off + r] = k;
-    }
+    for (int r = 0; r < c.h_rank[k]; ++r) c.h_colmodel[off + r] = k;
     off += c.h_rank[k];
     goff += (int64_t)c.h_rank[k] * c.h_rank[k];
   }
@@ -759,10 +778,9 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
   c.iters = static_cast<int32_t*>(take(it++));
   c.d_off = static_cast<int32_t*>(take(it++));
   c.d_rank = static_cast<int32_t*>(take(it++));
-  c.d_left = static_cast<int32_t*>(take(it++));
+  c.d_lomask = static_cast<uint8_t*>(take(it++));
   c.d_order = static_cast<int32_t*>(take(it++));
   c.d_goff = static_cast<int64_t*>(take(it++));
-  c.d_colp = static_cast<int32_t*>(take(it++));
   c.d_colmodel = static_cast<int32_t*>(take(it++));
   c.slice = static_cast<double*>(take(it++));
   c.slice_part = static_cast<double*>(take(it++));
@@ -776,10 +794,9 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
   // model tables (host vectors live in the context, so the copies are safe)
   JKC_HIP(hipMemcpyAsync(c.d_off, c.h_off.data(), pl.K * 4, hipMemcpyHostToDevice, st));
   JKC_HIP(hipMemcpyAsync(c.d_rank, c.h_rank.data(), pl.K * 4, hipMemcpyHostToDevice, st));
-  JKC_HIP(hipMemcpyAsync(c.d_left, c.h_left.data(), pl.K * 4, hipMemcpyHostToDevice, st));
+  JKC_HIP(hipMemcpyAsync(c.d_lomask, c.h_lomask.data(), c.h_lomask.size(), hipMemcpyHostToDevice, st));
   JKC_HIP(hipMemcpyAsync(c.d_order, c.h_order.data(), pl.K * 4, hipMemcpyHostToDevice, st));
   JKC_HIP(hipMemcpyAsync(c.d_goff, c.h_goff.data(), pl.K * 8, hipMemcpyHostToDevice, st));
-  JKC_HIP(hipMemcpyAsync(c.d_colp, c.h_colp.data(), pl.ldc * 4, hipMemcpyHostToDevice, st));
   JKC_HIP(hipMemcpyAsync(c.d_colmodel, c.h_colmodel.data(), pl.ldc * 4, hipMemcpyHostToDevice, st));
 
   // tensor residency
@@ -808,11 +825,11 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
     const int chunks = (int)std::min<int64_t>(kSliceChunks, outer);
     JKC_HIP(launch_slice_norms(tensor, pl.tensor_f32, inner, (int32_t)I, outer, c.slice_part,
                                chunks, c.slice, st));
-    JKC_HIP(launch_model_norms(c.slice, (int32_t)I, c.d_left, pl.K, c.normT2, st));
+    JKC_HIP(launch_model_norms(c.slice, (int32_t)I, c.d_lomask, pl.K, c.normT2, st));
   }
   // multi-factors with the inserted zero rows, then Grams
   for (int n = 0; n < pl.N; ++n) {
-    JKC_HIP(launch_pack_factor(init[n], pl.C, (int32_t)pl.dims[n], pl.C, pl.ldc, c.d_colp,
+    JKC_HIP(launch_pack_factor(init[n], pl.C, (int32_t)pl.dims[n], pl.C, pl.ldc, c.left_out(),
                                n == pl.nhat ? 1 : 0, c.U[n], st));
   }
   for (int n = 0; n < pl.N; ++n) JKC_TRY(enqueue_gram(&c, n));
@@ -848,7 +865,7 @@ jkc_status jk_cals_mttkrp(jkc_ctx* ctx, int32_t mode, double* out) {
   JKC_TRY(enqueue_mttkrp(ctx, mode, t));
   const int splits = effective_splits(ctx, mode, t);
   JKC_HIP(launch_reduce(splits > 1 ? ctx->partial : ctx->Mbuf, splits, (int32_t)ctx->dims[mode],
-                        ctx->ldc, ctx->C, ctx->d_colp, mode == ctx->nhat ? 1 : 0, out, ctx->C,
+                        ctx->ldc, ctx->C, ctx->left_out(), mode == ctx->nhat ? 1 : 0, out, ctx->C,
                         ctx->stream));
   g_last_error.clear();
   return JKC_OK;
@@ -905,7 +922,7 @@ jkc_status jk_cals_set_factors(jkc_ctx* ctx, int32_t mode, const double* in, con
   JKC_TRY(check_ctx(ctx));
   JKC_TRY(check_mode(ctx, mode));
   if (!in) return fail(JKC_EINVAL, "in is NULL");
-  JKC_HIP(launch_pack_factor(in, ctx->C, (int32_t)ctx->dims[mode], ctx->C, ctx->ldc, ctx->d_colp,
+  JKC_HIP(launch_pack_factor(in, ctx->C, (int32_t)ctx->dims[mode], ctx->C, ctx->ldc, ctx->left_out(),
                              mode == ctx->nhat ? 1 : 0, ctx->U[mode], ctx->stream));
   JKC_TRY(enqueue_gram(ctx, mode));
   if (lambda) {
@@ -1042,7 +1059,7 @@ jkc_status jk_cals_tune(jkc_ctx* ctx, int32_t reps) {
           JKC_TRY(enqueue_mttkrp(ctx, n, t));
           if (eff > 1)
             JKC_HIP(launch_reduce(ctx->partial, eff, (int32_t)ctx->dims[n], ctx->ldc, ctx->ldc,
-                                  ctx->d_colp, n == ctx->nhat ? 1 : 0, ctx->Mbuf, ctx->ldc,
+                                  ctx->left_out(), n == ctx->nhat ? 1 : 0, ctx->Mbuf, ctx->ldc,
                                   ctx->stream));
           return JKC_OK;
         };

@@ -75,11 +75,16 @@ const std::vector<MttkrpVariant>& mttkrp_split3_variants();   // three bf16 term
 struct ModelTable {
   const int32_t* off;     // [K] first column
   const int32_t* rank;    // [K]
-  const int32_t* left;    // [K] left-out index or -1
+  const uint8_t* lomask;  // [I_nhat][K]: 1 where row i of the sampled mode is left out of model k
   const int64_t* goff;    // [K] offset of the model's R x R blocks in a Gram plane
   const int32_t* order;   // [K] models sorted by decreasing cost
   int32_t K;
 };
+
+// Row i of the sampled mode is left out of model k.
+__device__ inline bool left_out_row(const ModelTable& mt, int64_t i, int k) {
+  return mt.lomask[i * mt.K + k] != 0;
+}
 
 struct UpdateArgs {
   ModelTable mt;
@@ -147,8 +152,16 @@ struct GramArgs {
 };
 hipError_t launch_gram(const GramArgs& a, hipStream_t s);
 
+// Left-out rows of the sampled mode, as the kernels that clear them see
+// them: the owning model of every column ([ldc], -1 for padding) and the
+// row mask of the model table.
+struct LeftOut {
+  const int32_t* colmodel;
+  const uint8_t* lomask;
+  int32_t K;
+};
 hipError_t launch_reduce(const double* partial, int32_t splits, int32_t rows,
-                         int32_t ldc, int32_t ncols, const int32_t* colp,
+                         int32_t ldc, int32_t ncols, LeftOut lo,
                          int32_t zero_rows, double* out, int32_t ldo,
                          hipStream_t s);
 
@@ -165,10 +178,10 @@ hipError_t launch_split_unfold(const void* src, int32_t src_f32, int32_t N, cons
 hipError_t launch_slice_norms(const void* T, int32_t t_f32, int64_t inner,
                               int32_t I, int64_t outer, double* partial,
                               int32_t chunks, double* s_out, hipStream_t s);
-hipError_t launch_model_norms(const double* s, int32_t I, const int32_t* left,
+hipError_t launch_model_norms(const double* s, int32_t I, const uint8_t* lomask,
                               int32_t K, double* normT2, hipStream_t st);
 hipError_t launch_pack_factor(const double* src, int32_t lds, int32_t rows,
-                              int32_t C, int32_t ldc, const int32_t* colp,
+                              int32_t C, int32_t ldc, LeftOut lo,
                               int32_t zero_rows, double* dst, hipStream_t s);
 hipError_t launch_unpack(const double* src, int32_t ldc, int32_t rows,
                          int32_t C, double* dst, hipStream_t s);
@@ -217,7 +230,9 @@ struct jkc_ctx {
   int64_t P = 0;
   int32_t tensor_f32 = 0, precision = 0;
   hipStream_t stream = nullptr;
-  std::vector<int32_t> h_rank, h_left, h_off, h_order, h_colp, h_colmodel;
+  std::vector<int32_t> h_rank, h_left, h_off, h_order, h_colmodel;
+  std::vector<uint8_t> h_lomask;  // [I_nhat][K]
+  int32_t del_d = 1;              // rows left out per submodel
   std::vector<int64_t> h_goff;
   int64_t gsize = 0;  // doubles per Gram plane
   int32_t rmax = 0;   // largest model rank
@@ -244,9 +259,8 @@ struct jkc_ctx {
   int32_t* iters = nullptr;
   int32_t* d_off = nullptr;
   int32_t* d_rank = nullptr;
-  int32_t* d_left = nullptr;
+  uint8_t* d_lomask = nullptr;
   int32_t* d_order = nullptr;
-  int32_t* d_colp = nullptr;
   int32_t* d_colmodel = nullptr;
   int64_t* d_goff = nullptr;
   double* slice = nullptr;       // [I_nhat] slice norms
@@ -277,6 +291,7 @@ struct jkc_ctx {
   }
 
   jkc::ModelTable table() const {
-    return jkc::ModelTable{d_off, d_rank, d_left, d_goff, d_order, K};
+    return jkc::ModelTable{d_off, d_rank, d_lomask, d_goff, d_order, K};
   }
+  jkc::LeftOut left_out() const { return jkc::LeftOut{d_colmodel, d_lomask, K}; }
 };

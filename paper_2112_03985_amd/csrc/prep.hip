@@ -129,22 +129,29 @@ __global__ void k_slice_final(const double* part, int32_t chunks, int32_t I, dou
   }
 }
 
-// ||T_{-p}||^2 = sum_{i != p} s_i, ascending i (the full norm for p = -1).
-__global__ void k_model_norms(const double* s, int32_t I, const int32_t* left, int32_t K,
+// ||T_{-P}||^2 = sum of s_i over the rows i not left out of the model,
+// ascending i (the full norm for a model that leaves out nothing).
+__global__ void k_model_norms(const double* s, int32_t I, const uint8_t* lomask, int32_t K,
                               double* normT2) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
-    const int p = left[k];
     double t = 0.0;
     for (int i = 0; i < I; ++i)
-      if (i != p) t += s[i];
+      if (!lomask[(int64_t)i * K + k]) t += s[i];
     normT2[k] = t;
   }
 }
 
+// Row i of column c's model is left out (padding columns own no rows).
+__device__ inline bool row_left_out(const LeftOut& lo, int64_t i, int c) {
+  const int k = lo.colmodel[c];
+  return k >= 0 && lo.lomask[i * lo.K + k] != 0;
+}
+
 // dst[i][c] (ld ldc) = src[i][c] (ld lds) for c < C, 0 for C <= c < ldc;
-// row colp[c] is zeroed when zero_rows (the inserted zero row, Alg. 3).
+// the left-out rows of column c's model are zeroed when zero_rows (the
+// inserted zero rows, Alg. 3).
 __global__ void k_pack(const double* src, int32_t lds, int32_t rows, int32_t C, int32_t ldc,
-                       const int32_t* colp, int32_t zero_rows, double* dst) {
+                       LeftOut lo, int32_t zero_rows, double* dst) {
   const int64_t n = (int64_t)rows * ldc;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -153,7 +160,7 @@ __global__ void k_pack(const double* src, int32_t lds, int32_t rows, int32_t C, 
     double v = 0.0;
     if (c < C) {
       v = src[i * lds + c];
-      if (zero_rows && colp[c] == (int)i) v = 0.0;
+      if (zero_rows && row_left_out(lo, i, c)) v = 0.0;
     }
     dst[e] = v;
   }
@@ -181,8 +188,9 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
     p[e] = v;
 }
 
-// out[i][c] = sum_s partial[s][i][c]; row colp[c] set to 0 when zero_rows
-// (Case I: the left-out row of the sampled mode's MTTKRP).  A block covers
+// out[i][c] = sum_s partial[s][i][c]; the left-out rows of column c's model
+// set to 0 when zero_rows (Case I: the left-out rows of the sampled mode's
+// MTTKRP).  A block covers
 // 64 consecutive elements with kReduceGroups wavefronts: with many partials
 // wavefront q sums its contiguous quarter of the splits in ascending order
 // and the quarter sums are added in ascending q; with few partials
@@ -192,7 +200,7 @@ constexpr int kReduceGroups = 4;
 constexpr int kReduceQuarterMin = 16;
 __global__ void __launch_bounds__(64 * kReduceGroups)
 k_reduce(const double* partial, int32_t splits, int32_t rows, int32_t ldc, int32_t ncols,
-         const int32_t* colp, int32_t zero_rows, double* out, int32_t ldo) {
+         LeftOut lo, int32_t zero_rows, double* out, int32_t ldo) {
   __shared__ double part[kReduceGroups][64];
   const int64_t n = (int64_t)rows * ncols;
   const int64_t plane = (int64_t)rows * ldc;
@@ -227,7 +235,7 @@ k_reduce(const double* partial, int32_t splits, int32_t rows, int32_t ldc, int32
     if (q == 0 && ok) {
       double t = part[0][lane];
       for (int g = 1; g < groups; ++g) t += part[g][lane];
-      if (zero_rows && colp[c] == (int)i) t = 0.0;
+      if (zero_rows && row_left_out(lo, i, c)) t = 0.0;
       out[i * ldo + c] = t;
     }
     __syncthreads();
@@ -291,17 +299,17 @@ hipError_t launch_slice_norms(const void* T, int32_t t_f32, int64_t inner, int32
   return hipGetLastError();
 }
 
-hipError_t launch_model_norms(const double* s, int32_t I, const int32_t* left, int32_t K,
+hipError_t launch_model_norms(const double* s, int32_t I, const uint8_t* lomask, int32_t K,
                               double* normT2, hipStream_t st) {
-  hipLaunchKernelGGL(k_model_norms, dim3(grid_for(K)), dim3(256), 0, st, s, I, left, K, normT2);
+  hipLaunchKernelGGL(k_model_norms, dim3(grid_for(K)), dim3(256), 0, st, s, I, lomask, K, normT2);
   return hipGetLastError();
 }
 
 hipError_t launch_pack_factor(const double* src, int32_t lds, int32_t rows, int32_t C,
-                              int32_t ldc, const int32_t* colp, int32_t zero_rows, double* dst,
+                              int32_t ldc, LeftOut lo, int32_t zero_rows, double* dst,
                               hipStream_t s) {
   hipLaunchKernelGGL(k_pack, dim3(grid_for((int64_t)rows * ldc)), dim3(256), 0, s, src, lds,
-                     rows, C, ldc, colp, zero_rows, dst);
+                     rows, C, ldc, lo, zero_rows, dst);
   return hipGetLastError();
 }
 
@@ -325,13 +333,13 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
 }
 
 hipError_t launch_reduce(const double* partial, int32_t splits, int32_t rows, int32_t ldc,
-                         int32_t ncols, const int32_t* colp, int32_t zero_rows, double* out,
+                         int32_t ncols, LeftOut lo, int32_t zero_rows, double* out,
                          int32_t ldo, hipStream_t s) {
   const int64_t n = (int64_t)rows * ncols;
   if (n <= 0) return hipSuccess;
   const int64_t blocks = std::min<int64_t>((n + 63) / 64, 16384);
   hipLaunchKernelGGL(k_reduce, dim3((unsigned)blocks), dim3(64 * kReduceGroups), 0, s, partial,
-                     splits, rows, ldc, ncols, colp, zero_rows, out, ldo);
+                     splits, rows, ldc, ncols, lo, zero_rows, out, ldo);
   return hipGetLastError();
 }
 

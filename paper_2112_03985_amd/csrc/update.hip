@@ -10,11 +10,12 @@
 //   H = L L^T                                    (Cholesky; eigen
 //                                                 pseudoinverse fallback)
 //   U_n|k(i,:) = M_n|k(i,:) H^{-1}  for all rows (normal equations)
-//   row p of M is taken as 0 when n is the sampled mode (Case I; the
-//   re-zeroing step of Alg. 3 then holds automatically: 0 H^{-1} = 0)
+//   the model's left-out rows of M (one, or d for delete-d) are taken as 0
+//   when n is the sampled mode (Case I; the re-zeroing step of Alg. 3 then
+//   holds automatically: 0 H^{-1} = 0)
 //   lambda_r = ||U(:,r)||, U(:,r) /= lambda_r    (normalisation)
 //   G_n|k = U^T U, upper triangle mirrored       (exactly symmetric)
-// and after the last mode the submodel error with ||T_{-p}||^2 (Alg. 3
+// and after the last mode the submodel error with ||T_{-P}||^2 (Alg. 3
 // error step, with the identity's Gram term read with a plus sign).
 // Every reduction runs in a fixed order, so results are bitwise repeatable.
 #include "jkc_internal.hpp"
@@ -209,17 +210,18 @@ __device__ void cholesky_inverse(const double (*L)[kLd], double (*Linv)[kLd],
   __syncthreads();
 }
 
-// Row pass: U(i,:) = M(i,:) H^{-1} for every row i of the model's block (row
-// `zero_row` of M taken as 0); returns this thread's share of
-// sum_i U(i,:) . M(i,:) (for the error identity).
+// Row pass: U(i,:) = M(i,:) H^{-1} for every row i of the model's block (the
+// model's left-out rows of M taken as 0 when `zero`); returns this thread's
+// share of sum_i U(i,:) . M(i,:) (for the error identity).
 __device__ double row_pass(const double* __restrict__ M, double* __restrict__ U, int rows,
-                           int ldc, int off, int R, int zero_row, const double (*Hinv)[kLd]) {
+                           int ldc, int off, int R, bool zero, const ModelTable& mt, int k,
+                           const double (*Hinv)[kLd]) {
   double inner = 0.0;
   for (int e = threadIdx.x; e < rows * R; e += blockDim.x) {
     const int i = e / R, r = e % R;
     const double* mrow = M + (int64_t)i * ldc + off;
     double u = 0.0, m = 0.0;
-    if (i != zero_row) {
+    if (!(zero && left_out_row(mt, i, k))) {
       for (int q = 0; q < R; ++q) u += mrow[q] * Hinv[q][r];
       m = mrow[r];
     }
@@ -294,9 +296,8 @@ __global__ void __launch_bounds__(kThreads) k_update(const UpdateArgs a) {
     if (st & (JKC_ST_CONVERGED | JKC_ST_NONFINITE)) continue;  // frozen (block-uniform)
     const int R = a.mt.rank[k];
     const int off = a.mt.off[k];
-    const int p = a.mt.left[k];
     const int64_t goff = a.mt.goff[k];
-    const int zero_row = (a.n == a.nhat) ? p : -1;
+    const bool zero = a.n == a.nhat;
 
     build_h(a.G[0], a.G[1], a.G[2], a.G[3], a.N, a.n, goff, R, H);
     __syncthreads();
@@ -306,7 +307,7 @@ __global__ void __launch_bounds__(kThreads) k_update(const UpdateArgs a) {
     else
       jacobi_pinv(H, Wj, Vj, Hp, R, s_cs);
 
-    const double inner = row_pass(a.Mout, a.U, a.In, a.ldc, off, R, zero_row, Hp);
+    const double inner = row_pass(a.Mout, a.U, a.In, a.ldc, off, R, zero, a.mt, k, Hp);
     const double in_all = block_sum(inner, s_red);
 
     column_norms(a.U, a.In, a.ldc, off, R, s_lam);
@@ -385,9 +386,8 @@ __global__ void __launch_bounds__(kUpdThreads) k_update_lds(const UpdateArgs a) 
     if (st & (JKC_ST_CONVERGED | JKC_ST_NONFINITE)) continue;  // frozen (block-uniform)
     const int R = a.mt.rank[k];
     const int off = a.mt.off[k];
-    const int p = a.mt.left[k];
     const int64_t goff = a.mt.goff[k];
-    const int zero_row = (a.n == a.nhat) ? p : -1;
+    const bool zero = a.n == a.nhat;
     // per-model scalars of the error step, fetched now so that their latency
     // overlaps the update
     double pre_nt2 = 0.0, pre_fprev = 0.0;
@@ -436,7 +436,7 @@ __global__ void __launch_bounds__(kUpdThreads) k_update_lds(const UpdateArgs a) 
           const int e = e0 + u * (int)blockDim.x + t;
           if (e < nel) {
             const int i = e / R, r = e - (e / R) * R;
-            Ms[i * ld + r] = (i == zero_row) ? 0.0 : m[u];
+            Ms[i * ld + r] = (zero && left_out_row(a.mt, i, k)) ? 0.0 : m[u];
           }
         }
       }
@@ -665,8 +665,8 @@ __global__ void __launch_bounds__(kThreads) k_gram(const GramArgs a) {
 // each submodel of Alg. 3) is split over blocks of kUpdRows rows:
 //   k_solve_rows:    per (model, row chunk): H and H^{-1} (recomputed per
 //                    chunk, R <= 32), the chunk's rows of M summed from the
-//                    split-K partials in ascending split order (row p zero for
-//                    Case I), U = M H^{-1} (unnormalised) written to a staging
+//                    split-K partials in ascending split order (left-out
+//                    rows zero for Case I), U = M H^{-1} (unnormalised) written to a staging
 //                    buffer, and the chunk's U^T U (upper triangle) and
 //                    sum U .* M stored;
 //   k_finalize_rows: per (model, row chunk): the chunk sums added in chunk
@@ -703,9 +703,8 @@ __global__ void __launch_bounds__(kThreads) k_solve_rows(const UpdateArgs a) {
       continue;
     }
     const int off = a.mt.off[k];
-    const int p = a.mt.left[k];
     const int rows = min(kUpdRows, a.In - r0);
-    const int zero_row = (a.n == a.nhat && p >= 0) ? p - r0 : -1;
+    const bool zero = a.n == a.nhat;
     // H (other modes' Grams) and the chunk's rows of M: loads issued together
     build_h(a.G[0], a.G[1], a.G[2], a.G[3], a.N, a.n, goff, R, H);
     for (int e = t; e < rows * R; e += blockDim.x) {
@@ -722,7 +721,7 @@ __global__ void __launch_bounds__(kThreads) k_solve_rows(const UpdateArgs a) {
         for (int u = 0; u < kBatch; ++u) m += v[u];
       }
       for (; sp < a.splits; ++sp) m += src[(int64_t)sp * plane];
-      Ms[i][r] = (i == zero_row) ? 0.0 : m;
+      Ms[i][r] = (zero && left_out_row(a.mt, r0 + i, k)) ? 0.0 : m;
     }
     __syncthreads();
     const bool chol_ok = cholesky(H, L, R, &s_flag);
@@ -869,8 +868,9 @@ int persistent_grid(int K) {
 }
 
 // Gradient of the CP loss for one mode (all-at-once CP), per model:
-// grad = U H - M with H = *_{m != n} G_m; row p of the sampled mode is 0.
-// After the last mode the loss 1/2 (||T_{-p}||^2 + sum(H*G) - 2 sum(U*M)).
+// grad = U H - M with H = *_{m != n} G_m; the left-out rows of the sampled
+// mode are 0.  After the last mode the loss
+// 1/2 (||T_{-P}||^2 + sum(H*G) - 2 sum(U*M)).
 __global__ void __launch_bounds__(kThreads) k_grad(const GradArgs a) {
   __shared__ double H[kMaxRank][kLd];
   __shared__ double s_red[kThreads];
@@ -878,7 +878,6 @@ __global__ void __launch_bounds__(kThreads) k_grad(const GradArgs a) {
     const int k = a.mt.order[idx];
     const int R = a.mt.rank[k];
     const int off = a.mt.off[k];
-    const int p = a.mt.left[k];
     const int64_t goff = a.mt.goff[k];
     build_h(a.Gp[0], a.Gp[1], a.Gp[2], a.Gp[3], a.N, a.n, goff, R, H);
     __syncthreads();
@@ -888,7 +887,7 @@ __global__ void __launch_bounds__(kThreads) k_grad(const GradArgs a) {
       const double* urow = a.U + (int64_t)i * a.ldc + off;
       double g = 0.0;
       const double m = a.Mfull[(int64_t)i * a.ldc + off + r];
-      if (!(a.n == a.nhat && i == p)) {
+      if (!(a.n == a.nhat && left_out_row(a.mt, i, k))) {
         double uh = 0.0;
         for (int q = 0; q < R; ++q) uh += urow[q] * H[q][r];
         g = uh - m;

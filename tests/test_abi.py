@@ -6,6 +6,7 @@ import os
 import shutil
 import subprocess
 
+import numpy as np
 import pytest
 
 import paper_2112_03985_amd as jk
@@ -97,6 +98,22 @@ def test_null_arguments_rejected(L):
     assert L.jk_cals_init(ctypes.byref(prob), ctypes.c_void_p(0x1000), ptrs, ctypes.c_void_p(0x100000), ctypes.c_size_t(size.value - 1), ctypes.byref(ctx)) == jk.JKC_ENOMEM
     assert L.jk_cals_init(ctypes.byref(prob), ctypes.c_void_p(0x1000), ptrs, ctypes.c_void_p(0x100000), size, None) == jk.JKC_EINVAL
     assert ctx.value is None
+
+
+def test_delete_d_validation(L):
+    def status(lo, dims=(6, 5, 4), ranks=None):
+        lo = np.asarray(lo)
+        ranks = ranks or [2] * len(lo)
+        prob, keep = jk.make_problem(list(dims), 0, ranks, lo)
+        size = ctypes.c_size_t(0)
+        return L.jk_cals_workspace_size(ctypes.byref(prob), ctypes.byref(size)), size.value
+    ok, size2 = status([[-1, -1], [0, 1], [2, 5]])
+    assert ok == jk.JKC_OK and size2 > 0
+    assert status([[0, 0], [1, 2]])[0] == jk.JKC_EINVAL          # repeated sample
+    assert status([[-1, 3], [1, 2]])[0] == jk.JKC_EINVAL         # -1 mixed with a sample
+    assert status([[0, 6], [1, 2]])[0] == jk.JKC_EINVAL          # out of range
+    assert status([list(range(6))])[0] == jk.JKC_EINVAL          # leaves nothing
+    assert status([[0, 1, 2, 3, 4]])[0] == jk.JKC_OK             # d = I - 1
 
 
 def test_null_context_rejected(L):
