@@ -220,6 +220,17 @@ jkc_status jk_cals_refine(jkc_ctx *ctx, int32_t steps, double *loss);
 jkc_status jk_cals_jackknife_std(jkc_ctx *ctx, int32_t ref, int32_t first, int32_t count,
                                  double *const *std, int32_t *perm, double *sign);
 
+/* Convergence compaction in jk_cals_fit (on by default): at every
+ * convergence check, once a fifth of the columns the fused MTTKRP covers
+ * belong to converged or non-finite (frozen) models, the models still being
+ * fitted are moved to the front of the multi-factors so the MTTKRP covers
+ * only their columns; the canonical column layout is restored before
+ * jk_cals_fit returns.  Every model's arithmetic is unchanged (its columns'
+ * sums run in the same order wherever they sit), so results are bitwise the
+ * same with compaction on or off.  enable: 0 or 1 (JKC_EINVAL otherwise).
+ * Host only. */
+jkc_status jk_cals_set_compaction(jkc_ctx *ctx, int32_t enable);
+
 /* Time each candidate MTTKRP tiling of every mode on this problem and keep
  * the fastest (restores the factors it started with).  Synchronous.
  * Optional: a context works with its built-in choice without it. */

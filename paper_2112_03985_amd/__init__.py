@@ -96,6 +96,7 @@ def lib() -> ctypes.CDLL:
         "jk_cals_profile_read": (I32, [VP, VP, VP]),
         "jk_cals_set_tiling": (I32, [VP, I32, I32, I32]),
         "jk_cals_jackknife_std": (I32, [VP, I32, I32, I32, P(VP), VP, VP]),
+        "jk_cals_set_compaction": (I32, [VP, I32]),
         "jk_cals_remove_slice": (I32, [P(Problem), VP, I32, VP]),
         "jk_cals_destroy": (None, [VP]),
         "jk_cals_last_error": (ctypes.c_char_p, []),
@@ -328,6 +329,9 @@ class JkCals:
 
     def set_update_kernel(self, which: int):
         _check(lib().jk_cals_set_update_kernel(self.ctx, int(which)))
+
+    def set_compaction(self, enable: bool):
+        _check(lib().jk_cals_set_compaction(self.ctx, 1 if enable else 0))
 
     def set_sweep_graph(self, enable: bool):
         _check(lib().jk_cals_set_sweep_graph(self.ctx, 1 if enable else 0))

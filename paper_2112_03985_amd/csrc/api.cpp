@@ -115,6 +115,8 @@ struct Plan {
     // jackknife post-processing: matched components and signed inverse norms
     items.push_back({"jk_perm", (int64_t)ldc * 4});
     items.push_back({"jk_scale", (int64_t)N * ldc * 8});
+    // convergence compaction: column map of a relayout
+    items.push_back({"colmap", (int64_t)ldc * 4});
     total = 0;
     for (auto& it : items) total += align_up(std::max<int64_t>(it.bytes, 1), kAlign);
   }
@@ -441,7 +443,7 @@ jkc_status enqueue_mttkrp(jkc_ctx* ctx, int n, const Tiling& t) {
   a.M = (int32_t)ctx->dims[n];
   a.J = ctx->P / ctx->dims[n];
   a.ldc = ctx->ldc;
-  a.ncols = ctx->C;
+  a.ncols = ctx->C_act;
   a.mtiles = (int32_t)((a.M + t.bm() - 1) / t.bm());
   a.ntiles = (int32_t)((a.ncols + t.bn() - 1) / t.bn());
   int64_t kchunk = (a.J + t.splits - 1) / t.splits;
@@ -747,6 +749,8 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
     off += c.h_rank[k];
     goff += (int64_t)c.h_rank[k] * c.h_rank[k];
   }
+  c.h_off_canon = c.h_off;
+  c.C_act = pl.C;
   // most expensive models first (rank^2 work per row), stable by index
   c.h_order.resize(pl.K);
   std::iota(c.h_order.begin(), c.h_order.end(), 0);
@@ -789,6 +793,7 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
   for (int n = 0; n < pl.N; ++n) c.Uf[n] = static_cast<float*>(take(it++));
   c.jk_perm = static_cast<int32_t*>(take(it++));
   c.jk_scale = static_cast<double*>(take(it++));
+  c.d_colmap = static_cast<int32_t*>(take(it++));
 
   hipStream_t st = c.stream;
   // model tables (host vectors live in the context, so the copies are safe)
@@ -881,23 +886,95 @@ jkc_status jk_cals_sweep(jkc_ctx* ctx, int32_t nsweeps, double* fit) {
   return JKC_OK;
 }
 
+// Move every model's columns to the offsets new_off (a permutation of whole
+// column blocks; Gram blocks, flags and masks are indexed by model and do
+// not move): factors and lambda are gathered through a column map, the model
+// table is updated, and the MTTKRP then covers the first c_act columns.
+// Synchronises the stream (the host tables are rewritten).
+static jkc_status relayout(jkc_ctx* ctx, const std::vector<int32_t>& new_off, int32_t c_act) {
+  ctx->h_colmap.assign(ctx->C, 0);
+  for (int k = 0; k < ctx->K; ++k)
+    for (int r = 0; r < ctx->h_rank[k]; ++r) ctx->h_colmap[new_off[k] + r] = ctx->h_off[k] + r;
+  hipStream_t st = ctx->stream;
+  JKC_HIP(hipMemcpyAsync(ctx->d_colmap, ctx->h_colmap.data(), (size_t)ctx->C * 4,
+                         hipMemcpyHostToDevice, st));
+  for (int n = 0; n < ctx->N; ++n) {
+    const int32_t rows = (int32_t)ctx->dims[n];
+    JKC_HIP(launch_gather_cols(ctx->U[n], rows, ctx->ldc, ctx->C, ctx->d_colmap, ctx->Mbuf, st));
+    JKC_HIP(hipMemcpyAsync(ctx->U[n], ctx->Mbuf, (size_t)rows * ctx->ldc * 8,
+                           hipMemcpyDeviceToDevice, st));
+  }
+  JKC_HIP(launch_gather_cols(ctx->lambda, 1, ctx->ldc, ctx->C, ctx->d_colmap, ctx->Mbuf, st));
+  JKC_HIP(hipMemcpyAsync(ctx->lambda, ctx->Mbuf, (size_t)ctx->ldc * 8, hipMemcpyDeviceToDevice, st));
+  ctx->h_off = new_off;
+  ctx->h_colmodel.assign(ctx->ldc, -1);
+  for (int k = 0; k < ctx->K; ++k)
+    for (int r = 0; r < ctx->h_rank[k]; ++r) ctx->h_colmodel[ctx->h_off[k] + r] = k;
+  JKC_HIP(hipMemcpyAsync(ctx->d_off, ctx->h_off.data(), (size_t)ctx->K * 4, hipMemcpyHostToDevice, st));
+  JKC_HIP(hipMemcpyAsync(ctx->d_colmodel, ctx->h_colmodel.data(), (size_t)ctx->ldc * 4,
+                         hipMemcpyHostToDevice, st));
+  JKC_HIP(hipStreamSynchronize(st));
+  ctx->C_act = c_act;
+  drop_graph(ctx);
+  return JKC_OK;
+}
+
 jkc_status jk_cals_fit(jkc_ctx* ctx, int32_t max_iters, double tol, int32_t* iters, double* fit,
                        int32_t* status) {
   JKC_TRY(check_ctx(ctx));
   if (max_iters < 0) return fail(JKC_EINVAL, "max_iters must be >= 0");
   const int check_every = 5;
   const int conv = tol > 0.0 ? 1 : 0;
-  for (int t = 0; t < max_iters; ++t) {
-    for (int n = 0; n < ctx->N; ++n) JKC_TRY(enqueue_update(ctx, n, tol, conv));
+  std::vector<int32_t> st_host;
+  jkc_status result = JKC_OK;
+  for (int t = 0; t < max_iters && result == JKC_OK; ++t) {
+    for (int n = 0; n < ctx->N && result == JKC_OK; ++n) result = enqueue_update(ctx, n, tol, conv);
+    if (result != JKC_OK) break;
     ctx->lambda_is_one = false;
     if (conv && ((t + 1) % check_every == 0 || t + 1 == max_iters)) {
       int32_t active = 0;
-      JKC_HIP(launch_count_active(ctx->status, ctx->K, ctx->counter, ctx->stream));
-      JKC_HIP(hipMemcpyAsync(&active, ctx->counter, 4, hipMemcpyDeviceToHost, ctx->stream));
-      JKC_HIP(hipStreamSynchronize(ctx->stream));
+      if (launch_count_active(ctx->status, ctx->K, ctx->counter, ctx->stream) != hipSuccess ||
+          hipMemcpyAsync(&active, ctx->counter, 4, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+          hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        result = fail(JKC_EDEVICE, "convergence check failed");
+        break;
+      }
       if (active == 0) break;
+      // no copy of the status words while the active models alone could
+      // still fill more than four fifths of the computed columns
+      if (!ctx->compaction || (int64_t)active * ctx->rmax * 5 > (int64_t)ctx->C_act * 4) continue;
+      // compaction: once a fifth of the computed columns belong to frozen
+      // models, move the models still being fitted to the front (in model
+      // order) so that the fused MTTKRP covers only their columns
+      st_host.resize(ctx->K);
+      if (hipMemcpy(st_host.data(), ctx->status, (size_t)ctx->K * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+        result = fail(JKC_EDEVICE, "hipMemcpy of the status words failed");
+        break;
+      }
+      int32_t act_cols = 0;
+      for (int k = 0; k < ctx->K; ++k)
+        if (!(st_host[k] & (JKC_ST_CONVERGED | JKC_ST_NONFINITE))) act_cols += ctx->h_rank[k];
+      if (act_cols * 5 <= ctx->C_act * 4) {
+        std::vector<int32_t> new_off(ctx->K);
+        int32_t pos = 0;
+        for (int pass = 0; pass < 2; ++pass)
+          for (int k = 0; k < ctx->K; ++k) {
+            const bool frozen = st_host[k] & (JKC_ST_CONVERGED | JKC_ST_NONFINITE);
+            if (frozen == (pass == 1)) {
+              new_off[k] = pos;
+              pos += ctx->h_rank[k];
+            }
+          }
+        result = relayout(ctx, new_off, act_cols);
+      }
     }
   }
+  // back to the canonical layout, whatever happened above
+  if (ctx->h_off != ctx->h_off_canon) {
+    const jkc_status r2 = relayout(ctx, ctx->h_off_canon, ctx->C);
+    if (result == JKC_OK) result = r2;
+  }
+  if (result != JKC_OK) return result;
   if (iters) JKC_HIP(hipMemcpyAsync(iters, ctx->iters, ctx->K * 4, hipMemcpyDeviceToHost, ctx->stream));
   if (fit) JKC_HIP(hipMemcpyAsync(fit, ctx->fit, ctx->K * 8, hipMemcpyDeviceToHost, ctx->stream));
   if (status)
@@ -1016,6 +1093,14 @@ jkc_status jk_cals_jackknife_std(jkc_ctx* ctx, int32_t ref, int32_t first, int32
   if (sign)
     JKC_HIP(launch_jk_signs(ctx->jk_scale, ctx->ldc, ctx->N, a.first_off, count * R, sign,
                             ctx->stream));
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_set_compaction(jkc_ctx* ctx, int32_t enable) {
+  JKC_TRY(check_ctx(ctx));
+  if (enable != 0 && enable != 1) return fail(JKC_EINVAL, "enable must be 0 or 1");
+  ctx->compaction = enable != 0;
   g_last_error.clear();
   return JKC_OK;
 }

@@ -183,6 +183,8 @@ hipError_t launch_model_norms(const double* s, int32_t I, const uint8_t* lomask,
 hipError_t launch_pack_factor(const double* src, int32_t lds, int32_t rows,
                               int32_t C, int32_t ldc, LeftOut lo,
                               int32_t zero_rows, double* dst, hipStream_t s);
+hipError_t launch_gather_cols(const double* src, int32_t rows, int32_t ldc, int32_t C,
+                              const int32_t* map, double* dst, hipStream_t s);
 hipError_t launch_unpack(const double* src, int32_t ldc, int32_t rows,
                          int32_t C, double* dst, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
@@ -273,6 +275,13 @@ struct jkc_ctx {
   int split_max[jkc::kMaxOrder] = {1, 1, 1, 1};
   std::string describe[jkc::kMaxOrder];
   bool lambda_is_one = true;     // lambda folded into the last factor
+  // Convergence compaction (jk_cals_fit): the models still being fitted
+  // occupy the first C_act columns; C_act == C in the canonical layout.
+  int32_t C_act = 0;
+  bool compaction = true;
+  std::vector<int32_t> h_off_canon;   // offsets of the canonical layout
+  std::vector<int32_t> h_colmap;      // last relayout map, [C]
+  int32_t* d_colmap = nullptr;        // [ldc]
   int update_kernel = 0;         // 0 LDS-staged, 1 global, 2 row-parallel
   double* upart = nullptr;       // row-parallel update scratch
   int32_t* jk_perm = nullptr;     // jackknife matching: [ldc]

@@ -166,6 +166,19 @@ __global__ void k_pack(const double* src, int32_t lds, int32_t rows, int32_t C, 
   }
 }
 
+// dst[i][c] = src[i][map[c]] for c < C, 0 for C <= c < ldc (column
+// relayout of a multi-factor; rows x ldc, both leading dimension ldc).
+__global__ void k_gather_cols(const double* src, int32_t rows, int32_t ldc, int32_t C,
+                              const int32_t* map, double* dst) {
+  const int64_t n = (int64_t)rows * ldc;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / ldc;
+    const int c = (int)(e % ldc);
+    dst[e] = c < C ? src[i * ldc + map[c]] : 0.0;
+  }
+}
+
 __global__ void k_unpack(const double* src, int32_t ldc, int32_t rows, int32_t C, double* dst) {
   const int64_t n = (int64_t)rows * C;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
@@ -310,6 +323,13 @@ hipError_t launch_pack_factor(const double* src, int32_t lds, int32_t rows, int3
                               hipStream_t s) {
   hipLaunchKernelGGL(k_pack, dim3(grid_for((int64_t)rows * ldc)), dim3(256), 0, s, src, lds,
                      rows, C, ldc, lo, zero_rows, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_cols(const double* src, int32_t rows, int32_t ldc, int32_t C,
+                              const int32_t* map, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_cols, dim3(grid_for((int64_t)rows * ldc)), dim3(256), 0, s, src,
+                     rows, ldc, C, map, dst);
   return hipGetLastError();
 }
 
