@@ -42,6 +42,8 @@ def _compare_iteration(wl, ctx, res, t, models=None, tol=TOL):
     (22, (9, 12, 7, 6), [2, 3], [8, -1], 0),
     (23, (15, 24, 10), [3, 3, 5], [4, -1, 23], 1),
     (24, (40, 33), [2, 3], [-1, 7], 0),
+    # multi-start CALS without jackknife: every model fitted to all of T
+    (31, (20, 15, 12), [2, 3, 4, 5, 3, 2], [-1] * 6, 0),
 ])
 def test_sweeps_match_oracle(seed, dims, ranks, lo, nh):
     wl = synth.random_problem(seed, dims, ranks, lo, noise=0.1, sampled_mode=nh)
