@@ -42,8 +42,11 @@
 // Tiles are BM x BN with BM = 16 WM TM covering all rows of small modes, so
 // each Khatri-Rao entry is generated once per column tile; blocks are dealt
 // to the XCDs in contiguous runs of column tiles (they share the tensor
-// slice in L2).  The next step's loads are issued before the matrix-core work
-// of the current step and stored after it (double-buffered LDS, one barrier).
+// slice in L2).  The loads of a step are issued two steps before it is
+// stored (two register stages), the store runs after the matrix-core work of
+// the step before it (double-buffered LDS, one barrier per step).
+#include <type_traits>
+
 #include "jkc_internal.hpp"
 
 namespace jkc {
@@ -51,6 +54,7 @@ namespace jkc {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -134,7 +138,6 @@ k_mttkrp_bf(const MttkrpArgs a) {
   // meet zero Khatri-Rao entries, and rows past I_n produce output rows that
   // are never stored (a non-finite tensor entry therefore only affects its
   // own output row, which is non-finite in the exact product too).
-  uint4 ra[AI][NTERM];
   const uint16_t* __restrict__ Tt[NTERM];
 #pragma unroll
   for (int t = 0; t < NTERM; ++t) Tt[t] = Tp + (int64_t)t * a.plane;
@@ -143,12 +146,21 @@ k_mttkrp_bf(const MttkrpArgs a) {
   Walk wb[BI];
 #pragma unroll
   for (int u = 0; u < BI; ++u) wb[u].init(a, kbeg + 8 * ((tid + NT * u) / BN));
-  float rlow[BI][8];         // the lowest other mode's 8 entries
-  float rhigh[BI][NO];       // the higher modes' entries (fast path)
-  bool bfast[BI], bok[BI];
   const uint32_t ldc = (uint32_t)a.ldc;
 
-  auto load_step = [&](int s) {
+  // Registers of the steps in flight, two stages indexed by a compile-time
+  // stage number: the loads of a step are issued two steps before its store
+  // (one wavefront per SIMD hides no latency by switching, so the distance
+  // has to come from the schedule).
+  u32x4 ra[2][AI][NTERM];
+  float rlow[2][BI][8];        // the lowest other mode's 8 entries
+  float rhigh[2][BI][NO];      // the higher modes' entries (fast path)
+  bool bfast[2][BI], bok[2][BI];
+  using S0_t = std::integral_constant<int, 0>;
+  using S1_t = std::integral_constant<int, 1>;
+
+  auto load_step = [&](auto P, int s) __attribute__((always_inline)) {
+    constexpr int p = decltype(P)::value;
     const int64_t j0 = kbeg + (int64_t)s * BK;
 #pragma unroll
     for (int u = 0; u < AI; ++u) {
@@ -159,7 +171,7 @@ k_mttkrp_bf(const MttkrpArgs a) {
       // element offset within a plane: below 2^31 (checked at init)
       const uint32_t at = ok ? (uint32_t)(i0 + row) * (uint32_t)a.ldt + (uint32_t)j : 0u;
 #pragma unroll
-      for (int t = 0; t < NTERM; ++t) ra[u][t] = *reinterpret_cast<const uint4*>(Tt[t] + at);
+      for (int t = 0; t < NTERM; ++t) ra[p][u][t] = *reinterpret_cast<const u32x4*>(Tt[t] + at);
     }
 #pragma unroll
     for (int u = 0; u < BI; ++u) {
@@ -167,10 +179,10 @@ k_mttkrp_bf(const MttkrpArgs a) {
       const int col = c0 + e % BN;
       const Walk& w = wb[u];
       const bool ok = e < BN * CH && col < a.ldc && w.j < kend;
-      bok[u] = ok;
+      bok[p][u] = ok;
       // fast path: the run neither wraps the lowest mode nor crosses kend
       const bool fast = ok && w.idx[0] + 8 <= (uint32_t)a.odim[0] && w.j + 8 <= kend;
-      bfast[u] = fast;
+      bfast[p][u] = fast;
       // float32 factor copies, 32-bit element offsets (below 2^31, checked
       // at init); rows i_low .. i_low+7 exist on the fast path, row 0 is read
       // eight times otherwise
@@ -179,22 +191,23 @@ k_mttkrp_bf(const MttkrpArgs a) {
       uint32_t o0 = (fast ? w.idx[0] : 0u) * ldc + cc;
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
-        rlow[u][v] = a.oUf[0][o0];
+        rlow[p][u][v] = a.oUf[0][o0];
         o0 += step;
       }
 #pragma unroll
-      for (int q = 1; q < NO; ++q) rhigh[u][q] = a.oUf[q][(ok ? w.idx[q] : 0u) * ldc + cc];
+      for (int q = 1; q < NO; ++q) rhigh[p][u][q] = a.oUf[q][(ok ? w.idx[q] : 0u) * ldc + cc];
     }
   };
 
-  auto store_step = [&](int buf) {
+  auto store_step = [&](auto P, int buf, int sdata) __attribute__((always_inline)) {
+    constexpr int p = decltype(P)::value;
 #pragma unroll
     for (int u = 0; u < AI; ++u) {
       const int e = tid + NT * u;
       if (e < BM * CH) {
         const int row = e / CH, run = e % CH;
 #pragma unroll
-        for (int t = 0; t < NTERM; ++t) *reinterpret_cast<uint4*>(&As[buf][t][row][8 * run]) = ra[u][t];
+        for (int t = 0; t < NTERM; ++t) *reinterpret_cast<u32x4*>(&As[buf][t][row][8 * run]) = ra[p][u][t];
       }
     }
 #pragma unroll
@@ -203,20 +216,22 @@ k_mttkrp_bf(const MttkrpArgs a) {
       if (e >= BN * CH) continue;
       const int cl = e % BN, run = e / BN;
       float f[8];
-      if (bfast[u]) {
+      if (bfast[p][u]) {
         float hi = 1.f;
 #pragma unroll
-        for (int q = NO - 1; q >= 1; --q) hi = (q == NO - 1) ? rhigh[u][q] : hi * rhigh[u][q];
+        for (int q = NO - 1; q >= 1; --q) hi = (q == NO - 1) ? rhigh[p][u][q] : hi * rhigh[p][u][q];
 #pragma unroll
-        for (int v = 0; v < 8; ++v) f[v] = NO == 1 ? rlow[u][v] : hi * rlow[u][v];
+        for (int v = 0; v < 8; ++v) f[v] = NO == 1 ? rlow[p][u][v] : hi * rlow[p][u][v];
       } else {
-        // runs that wrap, end the chunk or lie outside the tile: entry by entry
-        Walk w = wb[u];
+        // runs that wrap, end the chunk or lie outside the tile: entry by
+        // entry, from the run's first column
+        Walk w;
+        w.init(a, kbeg + (int64_t)sdata * BK + 8 * run);
         const int col = c0 + cl;
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
           float x = 0.f;
-          if (bok[u] && w.j < kend) {
+          if (bok[p][u] && w.j < kend) {
 #pragma unroll
             for (int q = NO - 1; q >= 0; --q) {
               const float y = a.oUf[q][w.idx[q] * ldc + (uint32_t)col];
@@ -241,8 +256,7 @@ k_mttkrp_bf(const MttkrpArgs a) {
           f[v] -= (float)h0;
           f[v + 1] -= (float)h1;
         }
-        *reinterpret_cast<uint4*>(&Bs[buf][t][cl][8 * run]) =
-            make_uint4(wds[0], wds[1], wds[2], wds[3]);
+        *reinterpret_cast<u32x4*>(&Bs[buf][t][cl][8 * run]) = u32x4{wds[0], wds[1], wds[2], wds[3]};
       }
     }
   };
@@ -257,24 +271,33 @@ k_mttkrp_bf(const MttkrpArgs a) {
       acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
     }
 
+  // Pipeline: at the start of step s, LDS buffer s&1 holds step s, the
+  // stage of parity (s+1)&1 holds step s+1 and the other stage step s+2
+  // (loads possibly in flight).  Step s computes from LDS, stores step s+1
+  // into the other buffer, synchronises, and reuses the freed stage for the
+  // loads of step s+3.  Loads past the chunk fetch clamped addresses and are
+  // masked (zero Khatri-Rao entries), so they are issued unconditionally.
   if (nsteps > 0) {
-    load_step(0);
-    store_step(0);
+    load_step(S0_t{}, 0);
+    store_step(S0_t{}, 0, 0);
   }
   __syncthreads();
+  auto advance_all = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < BI; ++u) wb[u].advance(a, BK);
+  };
+  advance_all();
+  load_step(S1_t{}, 1);
+  advance_all();
+  load_step(S0_t{}, 2);
 
   const int arow = wm * TM * 16 + (lane & 15);
   const int bcol = wn * TN * 16 + (lane & 15);
   const int kq = 8 * (lane >> 4);
   int since_flush = 0;
-  for (int s = 0; s < nsteps; ++s) {
+  // one step; stage P holds step s+1 and receives step s+3 afterwards
+  auto step = [&](int s, auto P) __attribute__((always_inline)) {
     const int buf = s & 1;
-    const bool more = s + 1 < nsteps;
-    if (more) {
-#pragma unroll
-      for (int u = 0; u < BI; ++u) wb[u].advance(a, BK);
-      load_step(s + 1);
-    }
     bf16x8 bfr[NTERM][TN];
 #pragma unroll
     for (int t = 0; t < NTERM; ++t)
@@ -314,8 +337,14 @@ k_mttkrp_bf(const MttkrpArgs a) {
           }
       since_flush = 0;
     }
-    if (more) store_step(buf ^ 1);
+    if (s + 1 < nsteps) store_step(P, buf ^ 1, s + 1);
     __syncthreads();
+    advance_all();
+    load_step(P, s + 3);
+  };
+  for (int s = 0; s < nsteps; s += 2) {
+    step(s, S1_t{});
+    if (s + 1 < nsteps) step(s + 1, S0_t{});
   }
 
   // Epilogue: v_mfma_f32_16x16x32_bf16 leaves row 4*(l/16)+r, column l%16
