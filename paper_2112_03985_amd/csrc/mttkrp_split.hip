@@ -199,12 +199,37 @@ k_mttkrp_bf(const MttkrpArgs a) {
     }
   };
 
-  auto store_step = [&](auto P, int buf, int sdata) __attribute__((always_inline)) {
+  // The store of a step, in two parts.  store_main writes the tensor runs
+  // and every Khatri-Rao run by the run formula (the higher modes' product
+  // times the 8 entries of the lowest mode), branch-free so that it can be
+  // interleaved with the matrix instructions; store_fix then rewrites, entry
+  // by entry, the runs the formula does not cover (runs that wrap the lowest
+  // mode, end the chunk or lie outside the tile) -- the same thread's later
+  // LDS write wins.
+  auto store_run = [&](float (&f)[8], int buf, int cl, int run) __attribute__((always_inline)) {
+#pragma unroll
+    for (int t = 0; t < NTERM; ++t) {
+      uint32_t wds[4];
+#pragma unroll
+      for (int v = 0; v < 8; v += 2) {
+        // round-to-nearest-even conversion of two entries; the remainders
+        // are exact in float32
+        const __bf16 h0 = (__bf16)f[v];
+        const __bf16 h1 = (__bf16)f[v + 1];
+        wds[v / 2] = (uint32_t)__builtin_bit_cast(uint16_t, h0) |
+                     ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+        f[v] -= (float)h0;
+        f[v + 1] -= (float)h1;
+      }
+      *reinterpret_cast<u32x4*>(&Bs[buf][t][cl][8 * run]) = u32x4{wds[0], wds[1], wds[2], wds[3]};
+    }
+  };
+  auto store_main = [&](auto P, int buf) __attribute__((always_inline)) {
     constexpr int p = decltype(P)::value;
 #pragma unroll
     for (int u = 0; u < AI; ++u) {
       const int e = tid + NT * u;
-      if (e < BM * CH) {
+      if (AI * NT == BM * CH || e < BM * CH) {
         const int row = e / CH, run = e % CH;
 #pragma unroll
         for (int t = 0; t < NTERM; ++t) *reinterpret_cast<u32x4*>(&As[buf][t][row][8 * run]) = ra[p][u][t];
@@ -213,51 +238,43 @@ k_mttkrp_bf(const MttkrpArgs a) {
 #pragma unroll
     for (int u = 0; u < BI; ++u) {
       const int e = tid + NT * u;
-      if (e >= BN * CH) continue;
-      const int cl = e % BN, run = e / BN;
-      float f[8];
-      if (bfast[p][u]) {
+      if (BI * NT == BN * CH || e < BN * CH) {
+        const int cl = e % BN, run = e / BN;
+        float f[8];
         float hi = 1.f;
 #pragma unroll
         for (int q = NO - 1; q >= 1; --q) hi = (q == NO - 1) ? rhigh[p][u][q] : hi * rhigh[p][u][q];
 #pragma unroll
         for (int v = 0; v < 8; ++v) f[v] = NO == 1 ? rlow[p][u][v] : hi * rlow[p][u][v];
-      } else {
-        // runs that wrap, end the chunk or lie outside the tile: entry by
-        // entry, from the run's first column
-        Walk w;
-        w.init(a, kbeg + (int64_t)sdata * BK + 8 * run);
-        const int col = c0 + cl;
+        store_run(f, buf, cl, run);
+      }
+    }
+  };
+  auto store_fix = [&](auto P, int buf, int sdata) __attribute__((always_inline)) {
+    constexpr int p = decltype(P)::value;
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-          float x = 0.f;
-          if (bok[p][u] && w.j < kend) {
+    for (int u = 0; u < BI; ++u) {
+      const int e = tid + NT * u;
+      if (e >= BN * CH || bfast[p][u]) continue;
+      const int cl = e % BN, run = e / BN;
+      float f[8];
+      Walk w;
+      w.init(a, kbeg + (int64_t)sdata * BK + 8 * run);
+      const int col = c0 + cl;
 #pragma unroll
-            for (int q = NO - 1; q >= 0; --q) {
-              const float y = a.oUf[q][w.idx[q] * ldc + (uint32_t)col];
-              x = (q == NO - 1) ? y : x * y;
-            }
+      for (int v = 0; v < 8; ++v) {
+        float x = 0.f;
+        if (bok[p][u] && w.j < kend) {
+#pragma unroll
+          for (int q = NO - 1; q >= 0; --q) {
+            const float y = a.oUf[q][w.idx[q] * ldc + (uint32_t)col];
+            x = (q == NO - 1) ? y : x * y;
           }
-          f[v] = x;
-          w.advance(a, 1);
         }
+        f[v] = x;
+        w.advance(a, 1);
       }
-#pragma unroll
-      for (int t = 0; t < NTERM; ++t) {
-        uint32_t wds[4];
-#pragma unroll
-        for (int v = 0; v < 8; v += 2) {
-          // round-to-nearest-even conversion of two entries; the remainders
-          // are exact in float32
-          const __bf16 h0 = (__bf16)f[v];
-          const __bf16 h1 = (__bf16)f[v + 1];
-          wds[v / 2] = (uint32_t)__builtin_bit_cast(uint16_t, h0) |
-                       ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
-          f[v] -= (float)h0;
-          f[v + 1] -= (float)h1;
-        }
-        *reinterpret_cast<u32x4*>(&Bs[buf][t][cl][8 * run]) = u32x4{wds[0], wds[1], wds[2], wds[3]};
-      }
+      store_run(f, buf, cl, run);
     }
   };
 
@@ -279,7 +296,8 @@ k_mttkrp_bf(const MttkrpArgs a) {
   // masked (zero Khatri-Rao entries), so they are issued unconditionally.
   if (nsteps > 0) {
     load_step(S0_t{}, 0);
-    store_step(S0_t{}, 0, 0);
+    store_main(S0_t{}, 0);
+    store_fix(S0_t{}, 0, 0);
   }
   __syncthreads();
   auto advance_all = [&]() __attribute__((always_inline)) {
@@ -296,8 +314,13 @@ k_mttkrp_bf(const MttkrpArgs a) {
   const int kq = 8 * (lane >> 4);
   int since_flush = 0;
   // one step; stage P holds step s+1 and receives step s+3 afterwards
+  constexpr int NPROD = NTERM == 3 ? 6 : 3;
+  constexpr int NMF = TM * TN * NPROD;            // matrix instructions per step
+  constexpr int NRD = NTERM * (TN + TM);          // fragment reads per step
+  constexpr int NWR = NTERM * (AI + BI);          // LDS writes of the store
   auto step = [&](int s, auto P) __attribute__((always_inline)) {
     const int buf = s & 1;
+    __builtin_amdgcn_sched_barrier(0);
     bf16x8 bfr[NTERM][TN];
 #pragma unroll
     for (int t = 0; t < NTERM; ++t)
@@ -324,6 +347,21 @@ k_mttkrp_bf(const MttkrpArgs a) {
         accf[x][y] = c;
       }
     }
+    // the next step's store (the other LDS buffer, free since the last
+    // barrier) interleaved with the matrix instructions: the fragment reads
+    // first, then each matrix instruction followed by a few vector
+    // instructions, the LDS writes spread over the step
+    store_main(P, buf ^ 1);
+    __builtin_amdgcn_sched_group_barrier(0x100, NRD, 0);       // fragment reads
+#pragma unroll
+    for (int i = 0; i < NMF; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);       // matrix
+      __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);       // vector ALU
+      if (i % (NMF / NWR > 0 ? NMF / NWR : 1) == 0)
+        __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);     // LDS write
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    store_fix(P, buf ^ 1, s + 1);
     since_flush += BK;
     if (since_flush >= kFlushK) {
 #pragma unroll
@@ -337,7 +375,6 @@ k_mttkrp_bf(const MttkrpArgs a) {
           }
       since_flush = 0;
     }
-    if (s + 1 < nsteps) store_step(P, buf ^ 1, s + 1);
     __syncthreads();
     advance_all();
     load_step(P, s + 3);
