@@ -106,3 +106,30 @@ def test_benchmark_tensor_in_groups_of_four():
             for n in range(3):
                 assert rel(facs[n][:, cols(wl, k)], ref[n]) <= 1e-11, (t, k, n)
             assert abs(err[k] - r.e_hist[t - 1]) <= 1e-11 * r.normT2
+
+
+def test_fit_with_compaction_and_post_processing():
+    """Delete-d submodels of uneven convergence fitted with a tolerance:
+    compaction on and off give the same bits, and the jackknife deviations
+    of the delete-2 set match the oracle's on the oracle's own fits."""
+    rng_dims, R = (24, 15, 12), 3
+    groups = [[-1, -1]] + [[2 * g, 2 * g + 1] for g in range(12)]
+    wl = synth.random_problem(55, rng_dims, [R] * len(groups), groups, noise=0.05, true_rank=3)
+    say("delete-2 fit + jackknife")
+    a = make_ctx(wl)
+    b = make_ctx(wl)
+    b.set_compaction(False)
+    ia, fa, sa = a.fit(200, 1e-8)
+    ib, fb, sb = b.fit(200, 1e-8)
+    assert np.array_equal(ia, ib) and np.array_equal(sa, sb) and np.array_equal(fa, fb)
+    for n in range(3):
+        assert np.array_equal(to_np(a.get_factors(n)[0]), to_np(b.get_factors(n)[0]))
+    # post-processing of fits after a fixed number of sweeps on both paths
+    c = make_ctx(wl)
+    c.sweep(30)
+    S = c.jackknife_std(0, 1, wl.K - 1)
+    res = oracle.jk_als(np.asarray(wl.T), 0, wl.ranks, wl.left_out, wl.init, 30)
+    ref = oracle.jackknife_std([res[k].U for k in range(1, wl.K)], res[0].U, 0)
+    for n in (1, 2):
+        g, r = to_np(S[n]), ref[n]
+        assert np.max(np.abs(g - r)) <= 1e-7 * np.max(np.abs(r)), n
