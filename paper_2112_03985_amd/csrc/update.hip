@@ -30,12 +30,109 @@ constexpr int kThreads = 256;
 constexpr int kUpdThreads = 512;
 constexpr int kLd = kMaxRank + 1;   // LDS row pitch of R x R matrices
 
+// v from another lane of the same row of 16 lanes (DPP control Ctrl), both
+// 32-bit halves moved by the data-parallel-primitive path of the VALU (no
+// trip through the LDS unit).
+template <int Ctrl>
+__device__ inline double dpp_f64(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, Ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), Ctrl, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ inline double lane_f64(double v, int lane) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wavefront, every lane active: pairs, quads,
+// eighths and rows of 16 combine by DPP lane swaps (each step adds two equal
+// partial sums in either order, and a + b == b + a exactly, so every lane of
+// a row holds the same bits), then the four row sums in the fixed order
+// (r0 + r1) + (r2 + r3).  Every lane gets the result; the same lanes combine
+// in the same order on every run.
 __device__ inline double wave_sum(double v) {
-  // Butterfly over the 64 lanes; the same lanes combine in the same order on
-  // every run.
+  v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
+  v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
+  v += dpp_f64<0x141>(v);   // row_half_mirror: the other quad of the eight
+  v += dpp_f64<0x140>(v);   // row_mirror: the other eight of the row
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+
+// Orders LDS accesses of the lanes of one wavefront: a wavefront's LDS
+// operations execute in issue order, so keeping the compiler from moving
+// them across this point is enough (no block barrier).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cholesky H = L L^T and the columns of L^{-1} for R <= RB <= 32, by the 64
+// lanes of one wavefront, in registers: lane r holds row r of H and then of
+// L; each right-looking step broadcasts the pivot and the new column with
+// readlane, so there are no LDS round trips and no barriers.  Every entry
+// gets the same operations in the same order as in the left-looking form
+// (products with the earlier columns subtracted in ascending column order,
+// then the division by the pivot), hence the same bits.  A pivot that is
+// not finite or not above 64 eps R max_j H_jj fails the factorisation
+// (return false, X untouched).  Otherwise lane j forms column j of L^{-1}
+// (forward substitution against rows of L broadcast the same way) and stores
+// it to X (LDS, pitch ld).  Loops run to the compile-time bound RB with
+// uniform guards, so the row arrays stay in registers.
+template <int RB>
+__device__ __attribute__((always_inline)) inline bool chol_inv_regs(const double* H, double* X,
+                                                                    int ld, int R, int t) {
+  double arow[RB];
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  for (int c = 0; c < RB; ++c) arow[c] = (c < R && t < R) ? H[t * ld + c] : 0.0;
+  double maxdiag = 0.0;
+#pragma unroll
+  for (int j = 0; j < RB; ++j)
+    if (j < R) maxdiag = fmax(maxdiag, lane_f64(arow[j], j));
+  const double thresh = kPivotTolPerRank * R * maxdiag;
+  bool all_ok = true;
+#pragma unroll
+  for (int j = 0; j < RB; ++j) {
+    if (j < R) {
+      const double d = lane_f64(arow[j], j);
+      const bool ok = isfinite(d) && d > thresh && maxdiag > 0.0 && isfinite(maxdiag);
+      all_ok = all_ok && ok;
+      const double ljj = ok ? sqrt(d) : 1.0;
+      const double lj = t > j ? arow[j] / ljj : ljj;     // L[t][j] for t >= j
+      arow[j] = lj;
+#pragma unroll
+      for (int c = j + 1; c < RB; ++c) {
+        if (c < R) {
+          const double lc = lane_f64(lj, c);               // L[c][j]
+          if (t >= c) arow[c] -= lj * lc;
+        }
+      }
+    }
+  }
+  if (!all_ok) return false;
+  double x[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    if (r < R) {
+      double v = (r == t) ? 1.0 : 0.0;
+#pragma unroll
+      for (int q = 0; q < r; ++q) {
+        const double lrq = lane_f64(arow[q], r);           // L[r][q]
+        if (q >= t) v -= lrq * x[q];
+      }
+      x[r] = (r < t) ? 0.0 : v / lane_f64(arow[r], r);
+    }
+  }
+  if (t < R) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      if (r < R) X[r * ld + t] = x[r];
+  }
+  return true;
 }
 
 // Sum of one value per thread in a fixed order: butterfly within each
@@ -382,93 +479,128 @@ __global__ void __launch_bounds__(kUpdThreads) k_update_lds(const UpdateArgs a) 
     // one model per block when the grid covers them all (the cost order only
     // matters for a persistent grid): saves a dependent load
     const int k = (int)gridDim.x >= a.mt.K ? idx : a.mt.order[idx];
+    // every per-model scalar in one round of loads: the frozen check comes
+    // after them, so the table lookups do not wait for the status
     const int32_t st = a.status[k];
-    if (st & (JKC_ST_CONVERGED | JKC_ST_NONFINITE)) continue;  // frozen (block-uniform)
     const int R = a.mt.rank[k];
     const int off = a.mt.off[k];
     const int64_t goff = a.mt.goff[k];
+    // per-model scalars of the error step, fetched now (by every thread, with
+    // no branch: a branch would make the compiler wait for them here) so that
+    // their latency overlaps the update
+    const double pre_nt2 = a.normT2[k];
+    const double pre_fprev = a.fit_prev[k];
+    const int32_t pre_it = a.iters[k];
+    if (st & (JKC_ST_CONVERGED | JKC_ST_NONFINITE)) continue;  // frozen (block-uniform)
     const bool zero = a.n == a.nhat;
-    // per-model scalars of the error step, fetched now so that their latency
-    // overlaps the update
-    double pre_nt2 = 0.0, pre_fprev = 0.0;
-    int32_t pre_it = 0;
-    if (t == 0 && a.last_mode) {
-      pre_nt2 = a.normT2[k];
-      pre_fprev = a.fit_prev[k];
-      pre_it = a.iters[k];
-    }
+    const int RR = R * R;
 
-    // H and the reduced block of M, loads issued together
-    for (int e = t; e < R * R; e += blockDim.x) {
-      const int r = e / R, c = e % R;
-      double h = 0.0;
-      bool first = true;
-#pragma unroll
-      for (int m = 0; m < kMaxOrder; ++m) {
-        if (m >= a.N || m == a.n) continue;
-        const double* Gm = m == 0 ? a.G[0] : m == 1 ? a.G[1] : m == 2 ? a.G[2] : a.G[3];
-        const double g = Gm[goff + e];
-        h = first ? g : h * g;
-        first = false;
-      }
-      H[r * ld + c] = h;
-    }
-    // M: kStage elements per thread per round, their loads issued before
-    // any of them is stored (one memory latency per round, not one per
-    // element); partials summed in ascending split order
+    // The Gram factors of H, loaded in the first round of M's loads, after
+    // them, and multiplied once M is stored (1.0 stands in for the skipped
+    // modes; x * 1.0 == x exactly, so the product keeps the ascending-mode
+    // order and bits of the oracle's).
+    constexpr int kHPer = (kMaxRank * kMaxRank + kUpdThreads - 1) / kUpdThreads;
+    double hg[kHPer][kMaxOrder];
+    // M: kStage elements per thread per round, their loads (and the left-out
+    // row flags) issued before any of them is stored (one memory latency per
+    // round); partials summed in ascending split order
     {
       constexpr int kStage = 4;
       const int nel = a.In * R;
-      for (int e0 = 0; e0 < nel; e0 += kStage * (int)blockDim.x) {
+      for (int e0 = 0; e0 == 0 || e0 < nel; e0 += kStage * kUpdThreads) {
         double m[kStage];
+        bool lo[kStage];
+        if (a.splits == 1 && nel > 0) {
 #pragma unroll
-        for (int u = 0; u < kStage; ++u) {
-          const int e = e0 + u * (int)blockDim.x + t;
-          m[u] = 0.0;
-          if (e < nel) {
-            const int i = e / R, r = e - (e / R) * R;
-            const double* src = a.partial + (int64_t)i * a.ldc + off + r;
-            for (int sp = 0; sp < a.splits; ++sp) m[u] += src[sp * plane];
+          for (int u = 0; u < kStage; ++u) {
+            const int e = e0 + u * kUpdThreads + t;
+            const int ec = e < nel ? e : 0;
+            const int i = ec / R, r = ec - (ec / R) * R;
+            m[u] = a.partial[(int64_t)i * a.ldc + off + r];
+            // the flag is loaded unconditionally (row 0 when this is not the
+            // sampled mode, whose rows may outnumber the flag table's) so no
+            // branch waits for it before the next element's loads
+            lo[u] = left_out_row(a.mt, zero ? i : 0, k) && zero;
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < kStage; ++u) {
+            const int e = e0 + u * kUpdThreads + t;
+            m[u] = 0.0;
+            lo[u] = false;
+            if (e < nel) {
+              const int i = e / R, r = e - (e / R) * R;
+              const double* src = a.partial + (int64_t)i * a.ldc + off + r;
+              for (int sp = 0; sp < a.splits; ++sp) m[u] += src[sp * plane];
+              lo[u] = zero && left_out_row(a.mt, i, k);
+            }
+          }
+        }
+        if (e0 == 0) {
+#pragma unroll
+          for (int u = 0; u < kHPer; ++u) {
+            const int e = t + u * kUpdThreads;
+            const int64_t ge = goff + (e < RR ? e : 0);
+#pragma unroll
+            for (int mm = 0; mm < kMaxOrder; ++mm)
+              hg[u][mm] = (mm < a.N && mm != a.n) ? a.G[mm][ge] : 1.0;
           }
         }
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
-          const int e = e0 + u * (int)blockDim.x + t;
+          const int e = e0 + u * kUpdThreads + t;
           if (e < nel) {
             const int i = e / R, r = e - (e / R) * R;
-            Ms[i * ld + r] = (zero && left_out_row(a.mt, i, k)) ? 0.0 : m[u];
+            Ms[i * ld + r] = lo[u] ? 0.0 : m[u];
           }
         }
       }
     }
-    __syncthreads();
-
-    // Cholesky, pivots by thread 0, the column below by threads i > j
-    double maxdiag = 0.0;
-    for (int j = 0; j < R; ++j) maxdiag = fmax(maxdiag, H[j * ld + j]);
-    const double thresh = kPivotTolPerRank * R * maxdiag;
-    if (t == 0) s_flag = 1;
-    for (int j = 0; j < R; ++j) {
-      if (t == 0) {
-        double d = H[j * ld + j];
-        for (int q = 0; q < j; ++q) d -= L[j * ld + q] * L[j * ld + q];
-        const bool ok = isfinite(d) && d > thresh && maxdiag > 0.0 && isfinite(maxdiag);
-        if (!ok) s_flag = 0;
-        L[j * ld + j] = ok ? sqrt(d) : 1.0;
+#pragma unroll
+    for (int u = 0; u < kHPer; ++u) {
+      const int e = t + u * kUpdThreads;
+      if (e < RR) {
+        double h = hg[u][0];
+#pragma unroll
+        for (int m = 1; m < kMaxOrder; ++m) h *= hg[u][m];
+        H[(e / R) * ld + e % R] = h;
       }
-      __syncthreads();
-      if (t > j && t < R) {
-        double v = H[t * ld + j];
-        for (int q = 0; q < j; ++q) v -= L[t * ld + q] * L[j * ld + q];
-        L[t * ld + j] = v / L[j * ld + j];
-      }
-      __syncthreads();
     }
-    const bool chol_ok = s_flag != 0;
     __syncthreads();
 
-    if (chol_ok) {
-      if (t < R) {
+    // Cholesky and L^{-1} in wavefront 0: in registers for R <= 8
+    // (chol_inv_regs), else in LDS with its steps ordered by wavefront-local
+    // syncs: pivots by lane 0, the column below by lanes i > j; then, if
+    // every pivot passed, lane j forms column j of L^{-1}
+    if (R <= 8) {
+      if (t < 64) {
+        const bool all_ok = chol_inv_regs<8>(H, X, ld, R, t);
+        if (t == 0) s_flag = all_ok ? 1 : 0;
+      }
+    } else if (t < 64) {
+      double maxdiag = 0.0;
+      for (int j = 0; j < R; ++j) maxdiag = fmax(maxdiag, H[j * ld + j]);
+      const double thresh = kPivotTolPerRank * R * maxdiag;
+      bool all_ok = true;
+      for (int j = 0; j < R; ++j) {
+        if (t == 0) {
+          double d = H[j * ld + j];
+          for (int q = 0; q < j; ++q) d -= L[j * ld + q] * L[j * ld + q];
+          const bool ok = isfinite(d) && d > thresh && maxdiag > 0.0 && isfinite(maxdiag);
+          all_ok = all_ok && ok;
+          L[j * ld + j] = ok ? sqrt(d) : 1.0;
+        }
+        wave_lds_sync();
+        if (t > j && t < R) {
+          double v = H[t * ld + j];
+          for (int q = 0; q < j; ++q) v -= L[t * ld + q] * L[j * ld + q];
+          L[t * ld + j] = v / L[j * ld + j];
+        }
+        wave_lds_sync();
+      }
+      if (t == 0) s_flag = all_ok ? 1 : 0;
+      wave_lds_sync();
+      if (s_flag != 0 && t < R) {
         const int j = t;
         for (int r = 0; r < R; ++r) {
           double v = (r == j) ? 1.0 : 0.0;
@@ -476,7 +608,11 @@ __global__ void __launch_bounds__(kUpdThreads) k_update_lds(const UpdateArgs a) 
           X[r * ld + j] = (r < j) ? 0.0 : v / L[r * ld + r];
         }
       }
-      __syncthreads();
+    }
+    __syncthreads();
+    const bool chol_ok = s_flag != 0;
+
+    if (chol_ok) {
       for (int e = t; e < R * R; e += blockDim.x) {
         const int r = e / R, c = e % R;
         if (r <= c) {
