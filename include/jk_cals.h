@@ -252,6 +252,20 @@ const char *jk_cals_describe(jkc_ctx *ctx, int32_t mode);
  * Host only. */
 jkc_status jk_cals_set_update_kernel(jkc_ctx *ctx, int32_t which);
 
+/* Shared partial contraction of a 3-way float64 sweep (Sec. 3: the MTTKRPs
+ * of Alg. 1 inside the concurrent sweep, evaluated as a two-level dimension
+ * tree; modes numbered from 0): at mode 0 the tensor is contracted once with
+ * the last factor, W(i,j,c) = sum_k T(i,j,k) U_2(k,c) for all active
+ * columns, and M_0 = sum_j W U_1, M_1 = sum_i W U_0 (U_0 just updated) are
+ * read from W; mode 2 keeps the fused MTTKRP.  The results equal the fused
+ * path's up to rounding (different summation order).  enable = 1 is the
+ * default when the problem is 3-way, float64, and W ([I_0 I_1] x ldc
+ * doubles, part of the workspace) stays below 2 GiB with I_0, I_1 <= 100000;
+ * JKC_EUNSUPPORTED for enable = 1 otherwise, EINVAL for other values.
+ * jk_cals_mttkrp, the gradient and refinement always use the fused MTTKRP.
+ * Host only. */
+jkc_status jk_cals_set_mttkrp_tree(jkc_ctx *ctx, int32_t enable);
+
 /* Replay multi-sweep runs of jk_cals_sweep from a HIP graph of one sweep,
  * captured on first use (enable = 1, default), or launch every kernel
  * directly (enable = 0).  The results are identical.  Host only. */

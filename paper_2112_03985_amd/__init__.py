@@ -92,6 +92,7 @@ def lib() -> ctypes.CDLL:
         "jk_cals_num_tilings": (I32, [VP]),
         "jk_cals_set_update_kernel": (I32, [VP, I32]),
         "jk_cals_set_sweep_graph": (I32, [VP, I32]),
+        "jk_cals_set_mttkrp_tree": (I32, [VP, I32]),
         "jk_cals_profile": (I32, [VP, I32]),
         "jk_cals_profile_read": (I32, [VP, VP, VP]),
         "jk_cals_set_tiling": (I32, [VP, I32, I32, I32]),
@@ -336,6 +337,9 @@ class JkCals:
     def set_sweep_graph(self, enable: bool):
         _check(lib().jk_cals_set_sweep_graph(self.ctx, 1 if enable else 0))
 
+    def set_mttkrp_tree(self, enable: bool):
+        _check(lib().jk_cals_set_mttkrp_tree(self.ctx, 1 if enable else 0))
+
     def num_tilings(self) -> int:
         return int(lib().jk_cals_num_tilings(self.ctx))
 
@@ -410,6 +414,10 @@ def jk_cals_set_update_kernel(ctx: JkCals, which: int):
 
 def jk_cals_set_sweep_graph(ctx: JkCals, enable: bool):
     return ctx.set_sweep_graph(enable)
+
+
+def jk_cals_set_mttkrp_tree(ctx: JkCals, enable: bool):
+    return ctx.set_mttkrp_tree(enable)
 
 
 def jk_cals_num_tilings(ctx: JkCals) -> int:

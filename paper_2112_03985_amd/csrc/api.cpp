@@ -64,6 +64,7 @@ struct Plan {
   int del_d = 1;   // rows of the sampled mode left out per submodel
   int split_max[kMaxOrder] = {1, 1, 1, 1};
   int64_t partial_doubles = 0;
+  int64_t tree_rows = 0;   // rows of W (3-way float64 sweeps), 0 when not held
 
   struct Item {
     const char* name;
@@ -117,6 +118,8 @@ struct Plan {
     items.push_back({"jk_scale", (int64_t)N * ldc * 8});
     // convergence compaction: column map of a relayout
     items.push_back({"colmap", (int64_t)ldc * 4});
+    // shared partial contraction of a 3-way sweep
+    items.push_back({"tree", tree_rows * ldc * 8});
     total = 0;
     for (auto& it : items) total += align_up(std::max<int64_t>(it.bytes, 1), kAlign);
   }
@@ -217,6 +220,13 @@ jkc_status make_plan(const jkc_problem* prob, Plan* pl) {
       pl->partial_doubles =
           std::max(pl->partial_doubles, (int64_t)pl->split_max[n] * pl->dims[n] * pl->ldc);
   }
+  // W = T x_2 U_2 for 3-way float64 problems, when it stays below 2 GiB
+  // (its rows i + I_0 j; the pass kernel's grid covers up to 131070 rows of
+  // each mode)
+  pl->tree_rows = 0;
+  if (pl->N == 3 && pl->precision == JKC_FP64 && pl->dims[0] <= 100000 && pl->dims[1] <= 100000 &&
+      pl->dims[0] * pl->dims[1] * (int64_t)pl->ldc * 8 < (int64_t(1) << 31))
+    pl->tree_rows = pl->dims[0] * pl->dims[1];
   pl->layout();
   return JKC_OK;
 }
@@ -306,6 +316,19 @@ ModeShape mode_shape(const jkc_ctx* ctx, int n, int split_max) {
   return s;
 }
 
+// W = T x_2 U_2 as the MTTKRP of the two-way view of T (rows i + I_0 j,
+// contraction over k): no split-K (its output alone fills the chip).
+ModeShape tree_shape(const jkc_ctx* ctx) {
+  ModeShape s;
+  s.M = ctx->dims[0] * ctx->dims[1];
+  s.J = ctx->dims[2];
+  s.ncols = ctx->C;
+  s.ldc = ctx->ldc;
+  s.split_max = 1;
+  s.buf_ok = ctx->P * (ctx->tensor_f32 ? 4 : 8) < kBufLimit && ctx->dims[2] * ctx->ldc * 8 < kBufLimit;
+  return s;
+}
+
 std::string describe_tiling(const Tiling& t, int precision) {
   char buf[128];
   const int fam = t.instr & 7;
@@ -333,11 +356,16 @@ std::mutex g_tune_mu;
 std::map<std::string, TuneEntry> g_tune;
 bool g_tune_loaded = false;
 
+// tuning-cache slot of the shared partial contraction's tiling
+constexpr int kTreeSlot = 99;
+
 std::string tune_key(const jkc_ctx* c, int n) {
   std::ostringstream o;
   o << "gfx950 p" << c->precision << " f32_" << c->tensor_f32 << " N" << c->N << " d";
   for (int m = 0; m < c->N; ++m) o << (m ? "x" : "") << c->dims[m];
-  o << " ldc" << c->ldc << " mode" << n;
+  o << " ldc" << c->ldc;
+  if (n == kTreeSlot) o << " tree";
+  else o << " mode" << n;
   return o.str();
 }
 
@@ -405,6 +433,8 @@ const std::vector<MttkrpVariant>& variants_for(const jkc_ctx* ctx) {
   return mttkrp_f64_variants();
 }
 
+jkc_status launch_mttkrp_timed(jkc_ctx* ctx, const MttkrpArgs& a, const Tiling& t, int pmode);
+
 // Enqueue the fused MTTKRP of mode n.  Result: split-K partials in
 // ctx->partial (t.splits > 1) or the product itself in ctx->Mbuf.
 jkc_status enqueue_mttkrp(jkc_ctx* ctx, int n, const Tiling& t) {
@@ -458,6 +488,13 @@ jkc_status enqueue_mttkrp(jkc_ctx* ctx, int n, const Tiling& t) {
   } else {
     a.partial = ctx->Mbuf;
   }
+  return launch_mttkrp_timed(ctx, a, t, n);
+}
+
+// Launch a filled MTTKRP, timed under mode pmode while jk_cals_profile is on.
+jkc_status launch_mttkrp_timed(jkc_ctx* ctx, const MttkrpArgs& a, const Tiling& t, int pmode) {
+  const auto& vars = variants_for(ctx);
+  const int n = pmode;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (ctx->prof_on && ctx->prof_used < kMaxTimedLaunches) {
     const size_t i = ctx->prof_used;
@@ -502,14 +539,81 @@ jkc_status enqueue_mttkrp_reduced(jkc_ctx* ctx, int n, double* out, int ldo, int
   return JKC_OK;
 }
 
+// W = T x_2 U_2 over the active columns (tree.hip explains the scheme):
+// the fused MTTKRP kernel on the two-way view of T, rows i + I_0 j (stride
+// 1), contraction over k (stride I_0 I_1); timed as mode 0's MTTKRP.
+jkc_status enqueue_tree_w(jkc_ctx* ctx) {
+  const Tiling& t = ctx->tree_tiling;
+  const auto& vars = variants_for(ctx);
+  if (t.variant < 0 || t.variant >= (int)vars.size()) return fail(JKC_ESTATE, "no tiling");
+  MttkrpArgs a{};
+  a.T = ctx->T;
+  a.plane = 0;
+  a.t_is_f32 = ctx->tensor_f32;
+  a.oU[0] = ctx->U[2];
+  a.odim[0] = (int32_t)ctx->dims[2];
+  a.ostride[0] = ctx->strides[2];
+  for (int q = 1; q < kMaxOrder - 1; ++q) {
+    a.oU[q] = nullptr;
+    a.odim[q] = 1;
+    a.ostride[q] = 0;
+  }
+  a.nother = 1;
+  a.stride_n = 1;
+  a.M = (int32_t)(ctx->dims[0] * ctx->dims[1]);
+  a.J = ctx->dims[2];
+  a.ldc = ctx->ldc;
+  a.ncols = ctx->C_act;
+  a.mtiles = (int32_t)((a.M + t.bm() - 1) / t.bm());
+  a.ntiles = (int32_t)((a.ncols + t.bn() - 1) / t.bn());
+  a.kchunk = align_up(a.J, t.bk);
+  a.splits = 1;
+  a.partial = ctx->Wtree;
+  JKC_TRY(launch_mttkrp_timed(ctx, a, t, 0));
+  ctx->tree_fresh = true;
+  return JKC_OK;
+}
+
+// M_n for n = 0 or 1 from W into Mbuf (rows of the left-out samples are
+// cleared by the update, as for the fused kernel).
+jkc_status enqueue_tree_pass(jkc_ctx* ctx, int n) {
+  const int64_t I0 = ctx->dims[0], I1 = ctx->dims[1];
+  if (n == 0)   // M_0(i, c) = sum_j W(i + I_0 j, c) U_1(j, c)
+    JKC_HIP(launch_tree_pass(ctx->Wtree, ctx->U[1], (int32_t)I1, 1, I0, (int32_t)I0, ctx->ldc,
+                             ctx->C_act, ctx->Mbuf, ctx->stream));
+  else          // M_1(j, c) = sum_i W(i + I_0 j, c) U_0(i, c)
+    JKC_HIP(launch_tree_pass(ctx->Wtree, ctx->U[0], (int32_t)I0, I0, 1, (int32_t)I1, ctx->ldc,
+                             ctx->C_act, ctx->Mbuf, ctx->stream));
+  return JKC_OK;
+}
+
 jkc_status enqueue_update(jkc_ctx* ctx, int n, double tol, int check_conv) {
   constexpr int64_t kLdsBudget = 64 * 1024;
   constexpr int kFuseMaxSplits = 2;
   const int64_t lds = update_lds_doubles(ctx->rmax, (int)ctx->dims[n]);
   const bool staged = ctx->update_kernel == 0 && lds * 8 <= kLdsBudget;
-  const int splits = effective_splits(ctx, n, ctx->tiling[n]);
+  // modes 0 and 1 of a 3-way sweep from the shared contraction W (mode 1
+  // only right after mode 0 has formed it)
+  const bool tree = ctx->use_tree && (n == 0 || (n == 1 && ctx->tree_fresh));
+  if (n != 0) ctx->tree_fresh = false;
+  const int splits = tree ? 1 : effective_splits(ctx, n, ctx->tiling[n]);
   UpdateArgs a{};
-  if (ctx->update_kernel == 2) {
+  if (tree) {
+    if (n == 0) JKC_TRY(enqueue_tree_w(ctx));
+    JKC_TRY(enqueue_tree_pass(ctx, n));
+    a.partial = ctx->Mbuf;
+    a.splits = 1;
+    if (ctx->update_kernel == 2) {
+      a.scratch = ctx->upart;
+      a.Utmp = ctx->Mbuf;
+      a.nch = (int32_t)((ctx->maxI + kUpdRows - 1) / kUpdRows);
+    } else if (staged) {
+      a.lds_doubles = lds;
+    } else {
+      a.partial = nullptr;
+      a.lds_doubles = 0;
+    }
+  } else if (ctx->update_kernel == 2) {
     // row-parallel: the solve kernel sums the split-K partials itself
     JKC_TRY(enqueue_mttkrp(ctx, n, ctx->tiling[n]));
     a.partial = splits > 1 ? ctx->partial : ctx->Mbuf;
@@ -794,6 +898,9 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
   c.jk_perm = static_cast<int32_t*>(take(it++));
   c.jk_scale = static_cast<double*>(take(it++));
   c.d_colmap = static_cast<int32_t*>(take(it++));
+  c.Wtree = static_cast<double*>(take(it++));
+  c.tree_avail = pl.tree_rows > 0;
+  c.use_tree = c.tree_avail;
 
   hipStream_t st = c.stream;
   // model tables (host vectors live in the context, so the copies are safe)
@@ -855,6 +962,11 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
     if (!tune_lookup(&c, n, vars, shape, &c.tiling[n])) c.tiling[n] = choose_tiling(vars, shape);
     c.describe[n] = describe_tiling(c.tiling[n], c.precision);
   }
+  if (c.tree_avail) {
+    const ModeShape shape = tree_shape(&c);
+    if (!tune_lookup(&c, kTreeSlot, vars, shape, &c.tree_tiling))
+      c.tree_tiling = choose_tiling(vars, shape);
+  }
   *out = ctx.release();
   g_last_error.clear();
   return JKC_OK;
@@ -892,6 +1004,7 @@ jkc_status jk_cals_sweep(jkc_ctx* ctx, int32_t nsweeps, double* fit) {
 // table is updated, and the MTTKRP then covers the first c_act columns.
 // Synchronises the stream (the host tables are rewritten).
 static jkc_status relayout(jkc_ctx* ctx, const std::vector<int32_t>& new_off, int32_t c_act) {
+  ctx->tree_fresh = false;
   ctx->h_colmap.assign(ctx->C, 0);
   for (int k = 0; k < ctx->K; ++k)
     for (int r = 0; r < ctx->h_rank[k]; ++r) ctx->h_colmap[new_off[k] + r] = ctx->h_off[k] + r;
@@ -1002,6 +1115,7 @@ jkc_status jk_cals_set_factors(jkc_ctx* ctx, int32_t mode, const double* in, con
   JKC_HIP(launch_pack_factor(in, ctx->C, (int32_t)ctx->dims[mode], ctx->C, ctx->ldc, ctx->left_out(),
                              mode == ctx->nhat ? 1 : 0, ctx->U[mode], ctx->stream));
   JKC_TRY(enqueue_gram(ctx, mode));
+  ctx->tree_fresh = false;
   if (lambda) {
     JKC_HIP(hipMemcpyAsync(ctx->lambda, lambda, ctx->C * 8, hipMemcpyDeviceToDevice, ctx->stream));
     ctx->lambda_is_one = false;
@@ -1124,9 +1238,12 @@ jkc_status jk_cals_tune(jkc_ctx* ctx, int32_t reps) {
       if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) break;
     }
   }
-  for (int n = 0; n < ctx->N && result == JKC_OK; ++n) {
-    const ModeShape shape = mode_shape(ctx, n, ctx->split_max[n]);
-    Tiling best = ctx->tiling[n];
+  // modes 0..N-1, then (slot N) the shared partial contraction if held
+  for (int n = 0; n <= ctx->N && result == JKC_OK; ++n) {
+    const bool is_tree = n == ctx->N;
+    if (is_tree && !ctx->tree_avail) break;
+    const ModeShape shape = is_tree ? tree_shape(ctx) : mode_shape(ctx, n, ctx->split_max[n]);
+    Tiling best = is_tree ? ctx->tree_tiling : ctx->tiling[n];
     float best_ms = std::numeric_limits<float>::infinity();
     for (int v = 0; v < (int)vars.size() && result == JKC_OK; ++v) {
       if (!usable(vars[v], shape)) continue;
@@ -1138,9 +1255,16 @@ jkc_status jk_cals_tune(jkc_ctx* ctx, int32_t reps) {
         if (ci == 2 && cands[2] == cands[1]) continue;
         Tiling t = base;
         t.splits = cands[ci];
-        const int eff = effective_splits(ctx, n, t);
+        const int eff = is_tree ? 1 : effective_splits(ctx, n, t);
         // warm-up, then timed repetitions of MTTKRP + reduction
         auto run = [&]() -> jkc_status {
+          if (is_tree) {
+            const Tiling keep = ctx->tree_tiling;
+            ctx->tree_tiling = t;
+            const jkc_status r = enqueue_tree_w(ctx);
+            ctx->tree_tiling = keep;
+            return r;
+          }
           JKC_TRY(enqueue_mttkrp(ctx, n, t));
           if (eff > 1)
             JKC_HIP(launch_reduce(ctx->partial, eff, (int32_t)ctx->dims[n], ctx->ldc, ctx->ldc,
@@ -1171,6 +1295,12 @@ jkc_status jk_cals_tune(jkc_ctx* ctx, int32_t reps) {
         }
       }
     }
+    if (is_tree) {
+      ctx->tree_tiling = best;
+      drop_graph(ctx);
+      if (result == JKC_OK) tune_store(ctx, kTreeSlot, best);
+      break;
+    }
     ctx->tiling[n] = best;
     ctx->describe[n] = describe_tiling(best, ctx->precision);
     drop_graph(ctx);
@@ -1192,6 +1322,18 @@ jkc_status jk_cals_set_update_kernel(jkc_ctx* ctx, int32_t which) {
   if (which < 0 || which > 2) return fail(JKC_EINVAL, "which must be 0, 1 or 2");
   ctx->update_kernel = which;
   drop_graph(ctx);
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_set_mttkrp_tree(jkc_ctx* ctx, int32_t enable) {
+  JKC_TRY(check_ctx(ctx));
+  if (enable != 0 && enable != 1) return fail(JKC_EINVAL, "enable must be 0 or 1");
+  if (enable && !ctx->tree_avail)
+    return fail(JKC_EUNSUPPORTED, "the shared contraction needs a 3-way float64 problem whose W fits");
+  if (ctx->use_tree != (enable != 0)) drop_graph(ctx);
+  ctx->use_tree = enable != 0;
+  ctx->tree_fresh = false;
   g_last_error.clear();
   return JKC_OK;
 }

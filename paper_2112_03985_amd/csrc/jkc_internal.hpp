@@ -160,6 +160,9 @@ struct LeftOut {
   const uint8_t* lomask;
   int32_t K;
 };
+hipError_t launch_tree_pass(const double* W, const double* F, int32_t S, int64_t ostep,
+                            int64_t sstep, int32_t nout, int32_t ldc, int32_t ncols, double* out,
+                            hipStream_t s);
 hipError_t launch_reduce(const double* partial, int32_t splits, int32_t rows,
                          int32_t ldc, int32_t ncols, LeftOut lo,
                          int32_t zero_rows, double* out, int32_t ldo,
@@ -287,6 +290,13 @@ struct jkc_ctx {
   int32_t* jk_perm = nullptr;     // jackknife matching: [ldc]
   double* jk_scale = nullptr;     // jackknife matching: [N][ldc]
   bool use_graph = true;         // replay sweeps from a captured HIP graph
+  // Shared partial contraction of a 3-way float64 sweep (tree.hip):
+  // W = T x_2 U_2, [I_0 I_1][ldc], computed at mode 0 and used by modes 0, 1
+  double* Wtree = nullptr;
+  bool tree_avail = false;       // the workspace holds W
+  bool use_tree = false;
+  bool tree_fresh = false;       // W matches U_2 of this sweep (host-side order)
+  jkc::Tiling tree_tiling;
   hipGraphExec_t graph_exec = nullptr;
 
   // MTTKRP kernel timing (jk_cals_profile)
