@@ -241,6 +241,8 @@ def main():
         ctx = jk.JkCals(T, wl.dims, 0, wl.ranks, wl.left_out, init, precision=precision)
         ctx.tune(5)
         tiling = [ctx.describe(n) for n in range(N)]
+        if ctx.describe(N):
+            tiling.append(ctx.describe(N))
         del ctx
 
     def step(profile=False):
@@ -278,6 +280,8 @@ def main():
     # fit quality and tilings of the last step (not timed)
     fit = c.get_status()[1].cpu().numpy()
     desc = [c.describe(n) for n in range(N)]
+    if c.describe(N):
+        desc.append(c.describe(N))
     # after the timed region: the MTTKRP with its split-K reduction (what a
     # caller of jk_cals_mttkrp gets), per mode, HIP events on the stream
     mout = torch.empty((max(wl.dims), C), dtype=torch.float64, device="cuda")
@@ -337,6 +341,10 @@ def main():
                 "traffic": measured_traffic(args.workload, prec_name, desc),
                 "kernel": kname, "avg_launch_ms": round(avg_ms, 5),
                 "per_mode_avg_ms": [round(float(kms[n] / max(launches[n], 1)), 5) for n in range(N)],
+                "timed_launches": ("per sweep: the shared contraction W = T x_2 U_2 (counted under mode 0; "
+                                   "modes 0 and 1 read W) and the fused MTTKRP of mode 2"
+                                   if any(d.startswith("tree") for d in desc) else
+                                   "per sweep: the fused MTTKRP of every mode"),
                 "flops_per_launch": flops_per_launch * issued}
 
     out = {"metric": "jackknife submodels fitted/sec (JK-CALS, %d sweeps each)" % sweeps,

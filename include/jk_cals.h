@@ -236,7 +236,10 @@ jkc_status jk_cals_set_compaction(jkc_ctx *ctx, int32_t enable);
  * Optional: a context works with its built-in choice without it. */
 jkc_status jk_cals_tune(jkc_ctx *ctx, int32_t reps);
 
-/* The current tiling of `mode` as text, e.g. "f64 wm2 wn2 tm2 tn2 bk16 s8". */
+/* The current tiling of `mode` as text, e.g. "f64 wm2 wn2 tm2 tn2 bk16 s8";
+ * mode = N names the shared partial contraction of 3-way sweeps ("tree ...",
+ * "" when sweeps do not use it).  "" for other modes or a NULL context.  The
+ * string stays valid until the next call on this context. */
 const char *jk_cals_describe(jkc_ctx *ctx, int32_t mode);
 
 /* Choose the per-model update (Alg. 3 update step): 0 = one block per

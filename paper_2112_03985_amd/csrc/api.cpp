@@ -1313,7 +1313,13 @@ jkc_status jk_cals_tune(jkc_ctx* ctx, int32_t reps) {
 }
 
 const char* jk_cals_describe(jkc_ctx* ctx, int32_t mode) {
-  if (!ctx || mode < 0 || mode >= ctx->N) return "";
+  if (!ctx || mode < 0 || mode > ctx->N) return "";
+  if (mode == ctx->N) {
+    // the shared partial contraction, when sweeps use it
+    if (!ctx->use_tree) return "";
+    ctx->tree_describe = "tree " + describe_tiling(ctx->tree_tiling, ctx->precision);
+    return ctx->tree_describe.c_str();
+  }
   return ctx->describe[mode].c_str();
 }
 

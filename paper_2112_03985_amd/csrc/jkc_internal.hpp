@@ -297,6 +297,7 @@ struct jkc_ctx {
   bool use_tree = false;
   bool tree_fresh = false;       // W matches U_2 of this sweep (host-side order)
   jkc::Tiling tree_tiling;
+  std::string tree_describe;
   hipGraphExec_t graph_exec = nullptr;
 
   // MTTKRP kernel timing (jk_cals_profile)

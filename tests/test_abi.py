@@ -131,6 +131,7 @@ def test_null_context_rejected(L):
     assert L.jk_cals_set_update_kernel(None, 0) == jk.JKC_EINVAL
     assert L.jk_cals_set_sweep_graph(None, 1) == jk.JKC_EINVAL
     assert L.jk_cals_set_compaction(None, 1) == jk.JKC_EINVAL
+    assert L.jk_cals_set_mttkrp_tree(None, 1) == jk.JKC_EINVAL
     assert L.jk_cals_profile(None, 1) == jk.JKC_EINVAL
     assert L.jk_cals_profile_read(None, None, None) == jk.JKC_EINVAL
     stds = (ctypes.c_void_p * 3)(0x1000, 0x1000, 0x1000)

@@ -1,0 +1,102 @@
+"""The shared partial contraction of 3-way float64 sweeps (W = T x_2 U_2 at
+mode 0, the MTTKRPs of modes 0 and 1 read from W): per-iteration parity with
+the oracle's independent per-submodel ALS at 1e-11 for every sampled mode,
+delete-d and shapes spanning several tiles with ragged tails; agreement with
+the fused MTTKRP path (rounding only); bitwise repeatability; refusal where
+W is not held."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_2112_03985_amd as jk
+from gpu_util import make_ctx, rel, say, to_np, cols
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [
+    # (seed, dims, ranks, left_out, sampled_mode)
+    (61, (37, 45, 23), [3, 5, 2, 4], [-1, 0, 36, 17], 0),
+    (62, (19, 26, 31), [4, 1, 6], [25, -1, 3], 1),
+    (63, (14, 11, 29), [2, 3, 3, 5, 1], [28, 0, -1, 13, 7], 2),
+    (64, (150, 70, 9), [5, 3, 7], [-1, 149, 64], 0),
+    (65, (23, 17, 40), [3, 2], [[4, 9, 16], [0, 1, 2]], 0),     # delete-3
+]
+
+
+@pytest.mark.parametrize("spec", SPECS, ids=[str(s[0]) for s in SPECS])
+def test_tree_sweeps_match_oracle(spec):
+    seed, dims, ranks, lo, nh = spec
+    wl = synth.random_problem(seed, dims, ranks, lo, noise=0.1, sampled_mode=nh)
+    sweeps = 4
+    say("tree sweep parity", seed, dims, nh)
+    res = oracle.jk_als(np.asarray(wl.T), nh, wl.ranks, wl.left_out, wl.init, sweeps,
+                        record_factors=range(1, sweeps + 1))
+    ctx = make_ctx(wl)
+    for t in range(1, sweeps + 1):
+        ctx.sweep(1)
+        err, fit = (to_np(x) for x in ctx.get_status()[:2])
+        lam = to_np(ctx.get_factors(0)[1])
+        facs = [to_np(ctx.get_factors(n)[0]) for n in range(3)]
+        for k, r in res.items():
+            c = cols(wl, k)
+            ref = r.padded(r.U_hist[t])
+            for n in range(3):
+                assert rel(facs[n][:, c], ref[n]) <= 1e-11, (t, k, n)
+            assert rel(lam[c], r.lam_hist[t - 1]) <= 1e-11
+            assert abs(err[k] - r.e_hist[t - 1]) <= 1e-11 * r.normT2, (t, k)
+            assert abs(fit[k] - r.fit_hist[t - 1]) <= 1e-9
+
+
+@pytest.mark.parametrize("spec", SPECS[:2] + SPECS[3:4], ids=["61", "62", "64"])
+def test_tree_and_fused_paths_agree(spec):
+    seed, dims, ranks, lo, nh = spec
+    wl = synth.random_problem(seed, dims, ranks, lo, noise=0.05, sampled_mode=nh)
+    say("tree vs fused", seed)
+    a, b, c = make_ctx(wl), make_ctx(wl), make_ctx(wl)
+    b.set_mttkrp_tree(False)
+    for x in (a, b, c):
+        x.sweep(6)
+    for n in range(3):
+        ua, la = (to_np(x) for x in a.get_factors(n))
+        ub, lb = (to_np(x) for x in b.get_factors(n))
+        uc = to_np(c.get_factors(n)[0])
+        assert rel(ua, ub) <= 1e-12 and rel(la, lb) <= 1e-12, n
+        assert np.array_equal(ua, uc), n              # bitwise repeatable
+    ea, eb = to_np(a.get_status()[0]), to_np(b.get_status()[0])
+    assert np.allclose(ea, eb, rtol=1e-11, atol=0)
+    # switching back and forth between sweeps keeps the iteration consistent
+    d = make_ctx(wl)
+    for s in range(6):
+        d.set_mttkrp_tree(s % 2 == 0)
+        d.sweep(1)
+    for n in range(3):
+        assert rel(to_np(d.get_factors(n)[0]), to_np(a.get_factors(n)[0])) <= 1e-12
+
+
+def test_tree_with_compaction_and_tolerance_fit():
+    wl = synth.random_problem(66, (30, 25, 20), [3] * 8, [-1] + list(range(7)), noise=0.02,
+                              true_rank=3)
+    say("tree fit + compaction")
+    a, b = make_ctx(wl), make_ctx(wl)
+    b.set_compaction(False)
+    ia, fa, sa = a.fit(300, 1e-9)
+    ib, fb, sb = b.fit(300, 1e-9)
+    assert np.array_equal(ia, ib) and np.array_equal(fa, fb) and np.array_equal(sa, sb)
+    for n in range(3):
+        assert np.array_equal(to_np(a.get_factors(n)[0]), to_np(b.get_factors(n)[0]))
+
+
+def test_tree_refused_where_not_held():
+    wl4 = synth.random_problem(67, (6, 5, 4, 3), [2, 2], [-1, 1])
+    ctx = make_ctx(wl4)
+    with pytest.raises(jk.JkcError):
+        ctx.set_mttkrp_tree(True)
+    ctx.set_mttkrp_tree(False)
+    wl2 = synth.random_problem(68, (9, 8), [2, 2], [-1, 3])
+    with pytest.raises(jk.JkcError):
+        make_ctx(wl2).set_mttkrp_tree(True)
+    wl3 = synth.random_problem(69, (9, 8, 7), [2, 2], [-1, 3])
+    with pytest.raises(jk.JkcError):
+        make_ctx(wl3, precision=jk.JKC_SPLIT_BF16X3).set_mttkrp_tree(True)
+    make_ctx(wl3).set_mttkrp_tree(True)
