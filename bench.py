@@ -42,6 +42,8 @@ def parse():
                     help="autotune the MTTKRP tilings (untimed) even for shapes in the shipped table")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-submodel GPU baseline")
+    ap.add_argument("--no-tree", action="store_true",
+                    help="fused MTTKRP on every mode (no shared partial contraction W = T x_2 U_2)")
     ap.add_argument("--plain-models", type=int, default=10)
     ap.add_argument("--cpu-models", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
@@ -73,6 +75,8 @@ def application_protocol(args, wl, T, init, precision, desc_w, prec_name):
 
     def one(compact):
         ctx = jk.JkCals(T, wl.dims, 0, wl.ranks, wl.left_out, init, precision=precision)
+        if args.no_tree and ctx.describe(len(wl.dims)):
+            ctx.set_mttkrp_tree(False)
         ctx.set_compaction(compact)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -247,6 +251,8 @@ def main():
 
     def step(profile=False):
         ctx = jk.JkCals(T, wl.dims, 0, wl.ranks, wl.left_out, init, precision=precision)
+        if args.no_tree and ctx.describe(N):
+            ctx.set_mttkrp_tree(False)
         if profile:
             ctx.profile(True)
         ctx.sweep(sweeps)

@@ -263,7 +263,8 @@ jkc_status jk_cals_set_update_kernel(jkc_ctx *ctx, int32_t which);
  * read from W; mode 2 keeps the fused MTTKRP.  The results equal the fused
  * path's up to rounding (different summation order).  enable = 1 is the
  * default when the problem is 3-way, float64, and W ([I_0 I_1] x ldc
- * doubles, part of the workspace) stays below 2 GiB with I_0, I_1 <= 100000;
+ * doubles, part of the workspace) takes at most 64 GiB with I_0, I_1 <=
+ * 100000;
  * JKC_EUNSUPPORTED for enable = 1 otherwise, EINVAL for other values.
  * jk_cals_mttkrp, the gradient and refinement always use the fused MTTKRP.
  * Host only. */
