@@ -964,8 +964,20 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
   }
   if (c.tree_avail) {
     const ModeShape shape = tree_shape(&c);
-    if (!tune_lookup(&c, kTreeSlot, vars, shape, &c.tree_tiling))
+    if (!tune_lookup(&c, kTreeSlot, vars, shape, &c.tree_tiling)) {
+      // untuned: the 16x16x4 tiling of 112 x 128 with four wavefronts, the
+      // tuner's choice on both measured shapes (100x200x200 at C = 500 and
+      // 300x250x200 at C = 82,500), else the cost model
       c.tree_tiling = choose_tiling(vars, shape);
+      for (int v = 0; v < (int)vars.size(); ++v) {
+        const auto& x = vars[v];
+        if (x.wm == 1 && x.wn == 4 && x.tm == 7 && x.tn == 2 && x.bk == 16 && x.instr == 24 &&
+            usable(x, shape)) {
+          c.tree_tiling = make_tiling(vars, v, shape, 1);
+          break;
+        }
+      }
+    }
   }
   *out = ctx.release();
   g_last_error.clear();

@@ -27,7 +27,7 @@ namespace jkc {
 namespace {
 
 constexpr int kPassWaves = 8;
-constexpr int kPassOut = 2;
+constexpr int kPassOut = 4;
 constexpr int kPassUnroll = 4;
 
 __global__ void __launch_bounds__(64 * kPassWaves)

@@ -100,3 +100,16 @@ def test_tree_refused_where_not_held():
     with pytest.raises(jk.JkcError):
         make_ctx(wl3, precision=jk.JKC_SPLIT_BF16X3).set_mttkrp_tree(True)
     make_ctx(wl3).set_mttkrp_tree(True)
+
+
+def test_describe_names_the_shared_contraction():
+    wl = synth.random_problem(70, (12, 10, 8), [2, 3], [-1, 4])
+    ctx = make_ctx(wl)
+    assert ctx.describe(3).startswith("tree f64 ")
+    assert ctx.describe(4) == "" and ctx.describe(-1) == ""
+    ctx.set_mttkrp_tree(False)
+    assert ctx.describe(3) == ""
+    ctx.set_mttkrp_tree(True)
+    assert ctx.describe(3).startswith("tree f64 ")
+    wl4 = synth.random_problem(71, (6, 5, 4, 3), [2], [-1])
+    assert make_ctx(wl4).describe(4) == ""
