@@ -271,8 +271,10 @@ jkc_status jk_cals_set_update_kernel(jkc_ctx *ctx, int32_t which);
 jkc_status jk_cals_set_mttkrp_tree(jkc_ctx *ctx, int32_t enable);
 
 /* Replay multi-sweep runs of jk_cals_sweep from a HIP graph of one sweep,
- * captured on first use (enable = 1, default), or launch every kernel
- * directly (enable = 0).  The results are identical.  Host only. */
+ * captured on first use (enable = 1), or launch every kernel directly
+ * (enable = 0, the default: on MI355X the direct launches of the benchmark
+ * sweep finish about 3 % sooner than the graph's).  The results are
+ * identical.  Host only. */
 jkc_status jk_cals_set_sweep_graph(jkc_ctx *ctx, int32_t enable);
 
 /* Number of MTTKRP tilings compiled for the context's precision (0 if ctx is

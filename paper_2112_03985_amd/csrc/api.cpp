@@ -513,10 +513,8 @@ jkc_status launch_mttkrp_timed(jkc_ctx* ctx, const MttkrpArgs& a, const Tiling& 
     ev0 = ctx->prof_ev[2 * i];
     ev1 = ctx->prof_ev[2 * i + 1];
     ++ctx->prof_used;
-    JKC_HIP(hipEventRecord(ev0, ctx->stream));
   }
-  JKC_HIP(vars[t.variant].launch(a, ctx->stream));
-  if (ev1) JKC_HIP(hipEventRecord(ev1, ctx->stream));
+  JKC_HIP(vars[t.variant].launch(a, ctx->stream, ev0, ev1));
   return JKC_OK;
 }
 

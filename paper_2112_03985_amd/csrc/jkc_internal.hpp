@@ -61,7 +61,8 @@ struct MttkrpArgs {
 // Kernel table entries (defined in the .hip files).
 struct MttkrpVariant {
   int wm, wn, tm, tn, bk;
-  hipError_t (*launch)(const MttkrpArgs&, hipStream_t);
+  // start/stop events (may be null) are stamped by the dispatch itself
+  hipError_t (*launch)(const MttkrpArgs&, hipStream_t, hipEvent_t, hipEvent_t);
   int instr;   // matrix instruction family (kernel specific, low 3 bits) |
                // 8 when the step uses the interleaved instruction schedule
 };
@@ -289,7 +290,7 @@ struct jkc_ctx {
   double* upart = nullptr;       // row-parallel update scratch
   int32_t* jk_perm = nullptr;     // jackknife matching: [ldc]
   double* jk_scale = nullptr;     // jackknife matching: [N][ldc]
-  bool use_graph = true;         // replay sweeps from a captured HIP graph
+  bool use_graph = false;        // replay sweeps from a captured HIP graph
   // Shared partial contraction of a 3-way float64 sweep (tree.hip):
   // W = T x_2 U_2, [I_0 I_1][ldc], computed at mode 0 and used by modes 0, 1
   double* Wtree = nullptr;

@@ -48,6 +48,8 @@
 // bitwise repeatable for a fixed tiling.
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "jkc_internal.hpp"
 
 namespace jkc {
@@ -501,23 +503,29 @@ k_mttkrp_f64(const MttkrpArgs a) {
   }
 }
 
+// With events, the dispatch stamps them itself (no separate event packets
+// between kernels).
 template <int WM, int WN, int TM, int TN, int BK, int INSTR, int NO, bool F32>
-void launch_one(const MttkrpArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_mttkrp_f64<WM, WN, TM, TN, BK, INSTR, NO, F32>),
-                     dim3(a.mtiles * a.ntiles * a.splits), dim3(64 * WM * WN), 0, s, a);
+void launch_one(const MttkrpArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 grid(a.mtiles * a.ntiles * a.splits), block(64 * WM * WN);
+  if (e0 || e1)
+    hipExtLaunchKernelGGL((k_mttkrp_f64<WM, WN, TM, TN, BK, INSTR, NO, F32>), grid, block, 0, s, e0, e1,
+                          0, a);
+  else
+    hipLaunchKernelGGL((k_mttkrp_f64<WM, WN, TM, TN, BK, INSTR, NO, F32>), grid, block, 0, s, a);
 }
 
 // One instantiation per (number of other modes, tensor element type), so
 // that the load and product loops are fully unrolled without branches.
 template <int WM, int WN, int TM, int TN, int BK, int INSTR>
-hipError_t launch_f64(const MttkrpArgs& a, hipStream_t s) {
+hipError_t launch_f64(const MttkrpArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   switch (a.nother * 2 + (a.t_is_f32 ? 1 : 0)) {
-    case 2: launch_one<WM, WN, TM, TN, BK, INSTR, 1, false>(a, s); break;
-    case 3: launch_one<WM, WN, TM, TN, BK, INSTR, 1, true>(a, s); break;
-    case 4: launch_one<WM, WN, TM, TN, BK, INSTR, 2, false>(a, s); break;
-    case 5: launch_one<WM, WN, TM, TN, BK, INSTR, 2, true>(a, s); break;
-    case 6: launch_one<WM, WN, TM, TN, BK, INSTR, 3, false>(a, s); break;
-    case 7: launch_one<WM, WN, TM, TN, BK, INSTR, 3, true>(a, s); break;
+    case 2: launch_one<WM, WN, TM, TN, BK, INSTR, 1, false>(a, s, e0, e1); break;
+    case 3: launch_one<WM, WN, TM, TN, BK, INSTR, 1, true>(a, s, e0, e1); break;
+    case 4: launch_one<WM, WN, TM, TN, BK, INSTR, 2, false>(a, s, e0, e1); break;
+    case 5: launch_one<WM, WN, TM, TN, BK, INSTR, 2, true>(a, s, e0, e1); break;
+    case 6: launch_one<WM, WN, TM, TN, BK, INSTR, 3, false>(a, s, e0, e1); break;
+    case 7: launch_one<WM, WN, TM, TN, BK, INSTR, 3, true>(a, s, e0, e1); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

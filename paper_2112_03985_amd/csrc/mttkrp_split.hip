@@ -47,6 +47,8 @@
 // the step before it (double-buffered LDS, one barrier per step).
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "jkc_internal.hpp"
 
 namespace jkc {
@@ -401,13 +403,20 @@ k_mttkrp_bf(const MttkrpArgs a) {
 }
 
 template <int WM, int WN, int TM, int TN, int NTERM>
-hipError_t launch_bf(const MttkrpArgs& a, hipStream_t s) {
+hipError_t launch_bf(const MttkrpArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const dim3 grid(a.mtiles * a.ntiles * a.splits);
   const dim3 block(64 * WM * WN);
+  // with events, the dispatch stamps them itself
+  auto go = [&](auto kernel) {
+    if (e0 || e1)
+      hipExtLaunchKernelGGL(kernel, grid, block, 0, s, e0, e1, 0, a);
+    else
+      hipLaunchKernelGGL(kernel, grid, block, 0, s, a);
+  };
   switch (a.nother) {
-    case 1: hipLaunchKernelGGL((k_mttkrp_bf<WM, WN, TM, TN, NTERM, 1>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_mttkrp_bf<WM, WN, TM, TN, NTERM, 2>), grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_mttkrp_bf<WM, WN, TM, TN, NTERM, 3>), grid, block, 0, s, a); break;
+    case 1: go(k_mttkrp_bf<WM, WN, TM, TN, NTERM, 1>); break;
+    case 2: go(k_mttkrp_bf<WM, WN, TM, TN, NTERM, 2>); break;
+    case 3: go(k_mttkrp_bf<WM, WN, TM, TN, NTERM, 3>); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -190,6 +190,7 @@ def test_graph_replays_match_direct_launches():
     import torch
     wl = synth.random_problem(30, (33, 26, 21), [4, 2, 5], [-1, 12, 32], noise=0.05)
     g = make_ctx(wl)
+    g.set_sweep_graph(True)
     d = make_ctx(wl)
     d.set_sweep_graph(False)
     for rep in range(4):
