@@ -173,7 +173,8 @@ jkc_status jk_cals_get_status(jkc_ctx *ctx, double *err, double *fit,
 /* Least-squares CP loss f_k = 1/2 ||T_{-P_k} - [[U^(k)]]||^2 per model for
  * the context's factors with lambda folded into the last mode (the
  * all-at-once formulation the paper cites in Sec. 2), and its gradient
- * dF/dU_n = U_n H_n - M_n for every mode (an all-mode fused MTTKRP), with
+ * dF/dU_n = U_n H_n - M_n for every mode (an all-mode MTTKRP: fused per
+ * mode, or through the shared contraction of jk_cals_set_mttkrp_tree), with
  * the left-out rows of the sampled mode held at 0.  lambda is folded into the
  * last factor first (and reset to 1).  loss: device [K] (may be NULL).  The
  * gradients stay in the workspace for jk_cals_get_grad.  Asynchronous. */
@@ -266,8 +267,10 @@ jkc_status jk_cals_set_update_kernel(jkc_ctx *ctx, int32_t which);
  * doubles, part of the workspace) takes at most 64 GiB with I_0, I_1 <=
  * 100000;
  * JKC_EUNSUPPORTED for enable = 1 otherwise, EINVAL for other values.
- * jk_cals_mttkrp, the gradient and refinement always use the fused MTTKRP.
- * Host only. */
+ * The all-mode MTTKRP of jk_cals_loss_grad / jk_cals_refine uses the same
+ * W (the factors are fixed there, so it serves modes 0 and 1 and the tensor
+ * is read twice instead of three times); jk_cals_mttkrp always runs the
+ * fused MTTKRP.  Host only. */
 jkc_status jk_cals_set_mttkrp_tree(jkc_ctx *ctx, int32_t enable);
 
 /* Replay multi-sweep runs of jk_cals_sweep from a HIP graph of one sweep,

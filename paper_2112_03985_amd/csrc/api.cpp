@@ -738,9 +738,19 @@ jkc_status enqueue_fold_lambda(jkc_ctx* ctx) {
 // All-mode gradient at the current factors (lambda folded), loss optional.
 jkc_status enqueue_loss_grad(jkc_ctx* ctx, double* loss) {
   JKC_TRY(enqueue_fold_lambda(ctx));
+  // all-mode MTTKRP with the factors fixed: for 3-way float64 problems one
+  // shared contraction W = T x_2 U_2 serves modes 0 and 1 (the tensor is read
+  // twice instead of three times, two thirds of the matrix-core flops)
+  const bool tree = ctx->use_tree;
+  if (tree) JKC_TRY(enqueue_tree_w(ctx));
+  ctx->tree_fresh = false;
   for (int n = 0; n < ctx->N; ++n) {
-    JKC_TRY(enqueue_mttkrp_reduced(ctx, n, ctx->Mbuf, ctx->ldc, ctx->ldc));
-    if (effective_splits(ctx, n, ctx->tiling[n]) == 1 && n == ctx->nhat) {
+    const bool from_w = tree && n < 2;
+    if (from_w)
+      JKC_TRY(enqueue_tree_pass(ctx, n));
+    else
+      JKC_TRY(enqueue_mttkrp_reduced(ctx, n, ctx->Mbuf, ctx->ldc, ctx->ldc));
+    if ((from_w || effective_splits(ctx, n, ctx->tiling[n]) == 1) && n == ctx->nhat) {
       // the direct product still carries row p: clear it through a reduce pass
       JKC_HIP(launch_reduce(ctx->Mbuf, 1, (int32_t)ctx->dims[n], ctx->ldc, ctx->ldc, ctx->left_out(),
                             1, ctx->Mbuf, ctx->ldc, ctx->stream));

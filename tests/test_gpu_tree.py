@@ -113,3 +113,27 @@ def test_describe_names_the_shared_contraction():
     assert ctx.describe(3).startswith("tree f64 ")
     wl4 = synth.random_problem(71, (6, 5, 4, 3), [2], [-1])
     assert make_ctx(wl4).describe(4) == ""
+
+
+@pytest.mark.parametrize("spec", SPECS[:3], ids=["61", "62", "63"])
+def test_gradient_with_and_without_the_shared_contraction(spec):
+    """The all-mode MTTKRP of the loss gradient through W agrees with the
+    fused per-mode MTTKRPs (rounding only), for every sampled mode."""
+    import torch
+    seed, dims, ranks, lo, nh = spec
+    wl = synth.random_problem(seed, dims, ranks, lo, noise=0.1, sampled_mode=nh)
+    say("tree gradient", seed)
+    a, b = make_ctx(wl), make_ctx(wl)
+    b.set_mttkrp_tree(False)
+    la = torch.empty(wl.K, dtype=torch.float64, device="cuda")
+    lb = torch.empty_like(la)
+    a.loss_grad(la)
+    b.loss_grad(lb)
+    assert np.allclose(to_np(la), to_np(lb), rtol=1e-12, atol=0)
+    for n in range(3):
+        ga, gb = to_np(a.get_grad(n)), to_np(b.get_grad(n))
+        assert rel(ga, gb) <= 1e-12, n
+    a.refine(5)
+    b.refine(5)
+    for n in range(3):
+        assert rel(to_np(a.get_factors(n)[0]), to_np(b.get_factors(n)[0])) <= 1e-11, n
