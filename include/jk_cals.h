@@ -111,6 +111,10 @@ typedef struct {
                                   leave-one-out, d > 1 = delete-d jackknife
                                   (Sec. 4.1: d zero rows padded and kept zero
                                   instead of one); d < dims[sampled_mode]   */
+  int32_t tree_max_gib;        /* cap on the shared contraction W of 3-way
+                                  float64 sweeps (jk_cals_set_mttkrp_tree) in
+                                  GiB of workspace: 0 = default (64), < 0 =
+                                  never hold W (fused MTTKRP on every mode) */
 } jkc_problem;
 
 /* Bytes of device workspace the problem needs.  Host only, no device work. */
@@ -264,8 +268,8 @@ jkc_status jk_cals_set_update_kernel(jkc_ctx *ctx, int32_t which);
  * read from W; mode 2 keeps the fused MTTKRP.  The results equal the fused
  * path's up to rounding (different summation order).  enable = 1 is the
  * default when the problem is 3-way, float64, and W ([I_0 I_1] x ldc
- * doubles, part of the workspace) takes at most 64 GiB with I_0, I_1 <=
- * 100000;
+ * doubles, part of the workspace) fits jkc_problem.tree_max_gib (default
+ * 64 GiB) with I_0, I_1 <= 100000;
  * JKC_EUNSUPPORTED for enable = 1 otherwise, EINVAL for other values.
  * The all-mode MTTKRP of jk_cals_loss_grad / jk_cals_refine uses the same
  * W (the factors are fixed there, so it serves modes 0 and 1 and the tensor

@@ -55,6 +55,7 @@ class Problem(ctypes.Structure):
         ("copy_tensor", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
         ("delete_d", ctypes.c_int32),
+        ("tree_max_gib", ctypes.c_int32),
     ]
 
 
@@ -141,7 +142,7 @@ def to_device_tensor(T: np.ndarray, device="cuda"):
 
 
 def make_problem(dims, sampled_mode, ranks, left_out, tensor_dtype=JKC_TENSOR_F64,
-                 precision=JKC_FP64, copy_tensor=1, stream=0):
+                 precision=JKC_FP64, copy_tensor=1, stream=0, tree_max_gib=0):
     """Build the C problem descriptor; the returned tuple keeps the host
     arrays alive.  left_out is [K] (leave-one-out) or [K, d] (delete-d:
     row k lists the d samples model k leaves out, or d times -1)."""
@@ -152,7 +153,8 @@ def make_problem(dims, sampled_mode, ranks, left_out, tensor_dtype=JKC_TENSOR_F6
     flat = lo_np.reshape(-1)
     lo = (ctypes.c_int32 * len(flat))(*[int(x) for x in flat])
     prob = Problem(len(dims), d, int(sampled_mode), len(ranks), r, lo, int(tensor_dtype),
-                   int(precision), int(copy_tensor), ctypes.c_void_p(stream), del_d)
+                   int(precision), int(copy_tensor), ctypes.c_void_p(stream), del_d,
+                   int(tree_max_gib))
     return prob, (d, r, lo)
 
 
@@ -161,9 +163,9 @@ def make_problem(dims, sampled_mode, ranks, left_out, tensor_dtype=JKC_TENSOR_F6
 # ---------------------------------------------------------------------------
 
 def jk_cals_workspace_size(dims, sampled_mode, ranks, left_out, tensor_dtype=JKC_TENSOR_F64,
-                           precision=JKC_FP64, copy_tensor=1) -> int:
+                           precision=JKC_FP64, copy_tensor=1, tree_max_gib=0) -> int:
     prob, keep = make_problem(dims, sampled_mode, ranks, left_out, tensor_dtype, precision,
-                              copy_tensor, 0)
+                              copy_tensor, 0, tree_max_gib)
     out = ctypes.c_size_t(0)
     _check(lib().jk_cals_workspace_size(ctypes.byref(prob), ctypes.byref(out)))
     return int(out.value)
@@ -175,7 +177,7 @@ class JkCals:
 
     def __init__(self, tensor, dims: Sequence[int], sampled_mode: int, ranks, left_out,
                  init: Sequence, precision: int = JKC_FP64, copy_tensor: bool = True,
-                 stream=None):
+                 stream=None, tree_max_gib: int = 0):
         import torch
         self.dims = [int(x) for x in dims]
         self.N = len(self.dims)
@@ -203,7 +205,7 @@ class JkCals:
         self.stream_handle = _stream(stream)
         self._prob, self._keep = make_problem(self.dims, sampled_mode, self.ranks, self.left_out,
                                               tdt, precision, 1 if copy_tensor else 0,
-                                              self.stream_handle)
+                                              self.stream_handle, tree_max_gib)
         size = ctypes.c_size_t(0)
         _check(lib().jk_cals_workspace_size(ctypes.byref(self._prob), ctypes.byref(size)))
         self.workspace_bytes = int(size.value)

@@ -220,12 +220,15 @@ jkc_status make_plan(const jkc_problem* prob, Plan* pl) {
       pl->partial_doubles =
           std::max(pl->partial_doubles, (int64_t)pl->split_max[n] * pl->dims[n] * pl->ldc);
   }
-  // W = T x_2 U_2 for 3-way float64 problems, when it takes at most 64 GiB
-  // of the workspace (its rows i + I_0 j; the pass kernel's grid covers up
-  // to 131070 rows of each mode)
+  // W = T x_2 U_2 for 3-way float64 problems, when it takes at most
+  // tree_max_gib GiB of the workspace (default 64; its rows i + I_0 j; the
+  // pass kernel's grid covers up to 131070 rows of each mode)
   pl->tree_rows = 0;
+  const int64_t tree_cap = prob->tree_max_gib == 0 ? (int64_t(64) << 30)
+                           : prob->tree_max_gib < 0 ? -1
+                                                    : (int64_t)prob->tree_max_gib << 30;
   if (pl->N == 3 && pl->precision == JKC_FP64 && pl->dims[0] <= 100000 && pl->dims[1] <= 100000 &&
-      pl->dims[0] * pl->dims[1] * (int64_t)pl->ldc * 8 <= (int64_t(64) << 30))
+      pl->dims[0] * pl->dims[1] * (int64_t)pl->ldc * 8 <= tree_cap)
     pl->tree_rows = pl->dims[0] * pl->dims[1];
   pl->layout();
   return JKC_OK;

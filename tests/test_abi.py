@@ -52,6 +52,22 @@ def test_workspace_size_valid_problem():
     assert _size(ranks=[32] * 20, left_out=[-1] * 20) > s
 
 
+def test_workspace_holds_the_shared_contraction_within_its_cap():
+    # 3-way float64: W = [I_0 I_1] x ldc doubles (ldc = 16 here), 256-aligned;
+    # an item of no bytes still takes one 256-byte slot
+    w = 4 * 5 * 16 * 8
+    w_aligned = (w + 255) // 256 * 256
+    assert _size() - _size(tree_max_gib=-1) == w_aligned - 256
+    assert _size(tree_max_gib=1) == _size()
+    # not held for 4-way or split-precision problems
+    assert _size(dims=[4, 5, 6, 3]) == _size(dims=[4, 5, 6, 3], tree_max_gib=-1)
+    assert _size(precision=1) == _size(precision=1, tree_max_gib=-1)
+    # a cap below W's size drops it: 2048 x 2048 x ldc 16 doubles = 512 MiB
+    big = dict(dims=[2048, 2048, 2])
+    assert _size(**big) - _size(tree_max_gib=-1, **big) == 2048 * 2048 * 16 * 8 - 256
+    assert _size(tree_max_gib=64, **big) == _size(**big)
+
+
 @pytest.mark.parametrize("kw,msg", [
     (dict(dims=[4]), "order"),
     (dict(dims=[2, 2, 2, 2, 2]), "order"),

@@ -100,6 +100,20 @@ def test_tree_refused_where_not_held():
     with pytest.raises(jk.JkcError):
         make_ctx(wl3, precision=jk.JKC_SPLIT_BF16X3).set_mttkrp_tree(True)
     make_ctx(wl3).set_mttkrp_tree(True)
+    # a problem whose cap excludes W: fused MTTKRP on every mode, W refused
+    import torch
+    T, init = (jk.to_device_tensor(wl3.T),
+               [torch.from_numpy(np.ascontiguousarray(u)).cuda() for u in wl3.init])
+    ctx = jk.JkCals(T, wl3.dims, 0, wl3.ranks, wl3.left_out, init, tree_max_gib=-1)
+    assert ctx.describe(3) == ""
+    with pytest.raises(jk.JkcError):
+        ctx.set_mttkrp_tree(True)
+    ref = make_ctx(wl3)
+    ref.set_mttkrp_tree(False)
+    ctx.sweep(3)
+    ref.sweep(3)
+    for n in range(3):
+        assert np.array_equal(to_np(ctx.get_factors(n)[0]), to_np(ref.get_factors(n)[0]))
 
 
 def test_describe_names_the_shared_contraction():
