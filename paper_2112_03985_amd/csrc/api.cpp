@@ -228,6 +228,7 @@ jkc_status make_plan(const jkc_problem* prob, Plan* pl) {
                            : prob->tree_max_gib < 0 ? -1
                                                     : (int64_t)prob->tree_max_gib << 30;
   if (pl->N == 3 && pl->precision == JKC_FP64 && pl->dims[0] <= 100000 && pl->dims[1] <= 100000 &&
+      pl->dims[0] * pl->dims[1] < (int64_t(1) << 31) &&   // W's rows are 32-bit in the kernel
       pl->dims[0] * pl->dims[1] * (int64_t)pl->ldc * 8 <= tree_cap)
     pl->tree_rows = pl->dims[0] * pl->dims[1];
   pl->layout();
