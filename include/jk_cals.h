@@ -65,7 +65,7 @@ typedef enum {
   JKC_ENOMEM = -2,        /* workspace smaller than jk_cals_workspace_size  */
   JKC_EDEVICE = -3,       /* a HIP runtime call failed                       */
   JKC_ESTATE = -4,        /* call not valid in the context's current state  */
-  JKC_EUNSUPPORTED = -5   /* valid request this build does not provide       */
+  JKC_EUNSUPPORTED = -5   /* valid request the library does not provide      */
 } jkc_status;
 
 typedef enum {
