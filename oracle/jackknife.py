@@ -210,9 +210,13 @@ def fd_grad(T: np.ndarray, U: Sequence[np.ndarray], h: float = 1e-3,
 
 
 def gd_refine(T: np.ndarray, U0: Sequence[np.ndarray], steps: int) -> List[np.ndarray]:
-    """Gradient refinement of one submodel (reading; not in the paper):
+    """Gradient refinement of one submodel (reading; not in the paper, which
+    only cites gradient-based all-at-once CP in Sec. 2):
     U_n <- U_n - eta * df/dU_n for all modes at once, with the step
-    eta = 1 / sum_n ||H_n||_F fixed from the factors at step 0."""
+    eta = 1 / sum_n ||H_n||_F fixed from the factors at step 0.  Pinned
+    against central differences of the dense loss and an explicitly formed
+    Khatri-Rao Gram (one step, three steps with the frozen step size, the
+    fixed point at an exact decomposition)."""
     U = [np.array(u, dtype=np.float64) for u in U0]
     G = [u.T @ u for u in U]
     eta = 1.0 / sum(np.linalg.norm(cp.hadamard_of_grams(G, n)) for n in range(len(U)))

@@ -110,3 +110,61 @@ def test_gradient_missing_hadamard_is_caught(monkeypatch):
     monkeypatch.setattr(jackknife, "grad", bad)
     monkeypatch.setattr(oracle, "grad", bad)
     _fails(J.test_gradient_matches_central_differences_pin12)
+
+
+# --- gradient refinement (reading of the all-at-once CP step rule) ---------
+
+import test_oracle_refine as Rf
+
+
+def _refine_with(eta_of, sequential=False, refresh=False):
+    """A refinement loop with one planted change (step norm, per-mode
+    sequential updates, or the step recomputed every iteration)."""
+    def bad(T, U0, steps):
+        U = [np.array(u, dtype=np.float64) for u in U0]
+        eta = eta_of(U)
+        for _ in range(steps):
+            if refresh:
+                eta = eta_of(U)
+            if sequential:
+                for n in range(len(U)):
+                    U[n] = U[n] - eta * jackknife.grad(T, U)[n]
+            else:
+                g = jackknife.grad(T, U)
+                U = [u - eta * gn for u, gn in zip(U, g)]
+        return U
+    return bad
+
+
+def _eta_frobenius(U):
+    G = [u.T @ u for u in U]
+    return 1.0 / sum(np.linalg.norm(cp.hadamard_of_grams(G, n)) for n in range(len(U)))
+
+
+def _eta_spectral(U):
+    G = [u.T @ u for u in U]
+    return 1.0 / sum(np.linalg.norm(cp.hadamard_of_grams(G, n), 2) for n in range(len(U)))
+
+
+def test_refine_sanity_of_the_harness(monkeypatch):
+    """The rewritten loop with nothing planted passes the pins (so the three
+    planted variants below fail for their plant, not for the harness)."""
+    monkeypatch.setattr(oracle, "gd_refine", _refine_with(_eta_frobenius))
+    Rf.test_one_step_is_simultaneous_descent_with_frobenius_step(*Rf.CASES[0])
+    Rf.test_step_size_is_frozen_at_the_first_step(*Rf.CASES[0])
+
+
+def test_refine_spectral_norm_step_is_caught(monkeypatch):
+    monkeypatch.setattr(oracle, "gd_refine", _refine_with(_eta_spectral))
+    _fails(Rf.test_one_step_is_simultaneous_descent_with_frobenius_step, *Rf.CASES[0])
+
+
+def test_refine_sequential_modes_is_caught(monkeypatch):
+    monkeypatch.setattr(oracle, "gd_refine", _refine_with(_eta_frobenius, sequential=True))
+    _fails(Rf.test_one_step_is_simultaneous_descent_with_frobenius_step, *Rf.CASES[0])
+
+
+def test_refine_recomputed_step_is_caught(monkeypatch):
+    monkeypatch.setattr(oracle, "gd_refine", _refine_with(_eta_frobenius, refresh=True))
+    Rf.test_one_step_is_simultaneous_descent_with_frobenius_step(*Rf.CASES[0])
+    _fails(Rf.test_step_size_is_frozen_at_the_first_step, *Rf.CASES[0])
