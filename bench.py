@@ -8,10 +8,15 @@ normalisation, per-submodel error).  Workload: 100 x 200 x 200 float64
 tensor shaped like fluorescence data (rank 5, 2 % noise), 100 leave-one-out
 submodels of rank 5, 100 sweeps each (the fixed-iteration protocol).
 
-Prints one JSON line.  `value` = submodels fitted per second.  Also reported:
-the MTTKRP kernel's roofline position (float64 MFMA), the same jackknife done
-the plain way on the same GPU (one submodel at a time on its explicitly
-reduced tensor), and the CPU oracle's rate on a bounded sample.
+Prints one JSON line.  `value` = submodels fitted per second with the
+library's default evaluation (for 3-way float64 sweeps a shared partial
+contraction serves two modes); `alg3_fused_per_mode` = the same jackknife
+with the fused MTTKRP of Alg. 3 on every mode, timed separately.  The
+`roofline` object is that fused MTTKRP with its split-K reduction (float64
+MFMA), averaged over every mode; the shared contraction is reported on its
+own (`tree_w`).  Also reported: the same jackknife done the plain way on the
+same GPU (one submodel at a time on its explicitly reduced tensor), and the
+CPU oracle's rate on a bounded sample.
 """
 import argparse
 import hashlib
@@ -46,9 +51,9 @@ def parse():
                     help="fused MTTKRP on every mode (no shared partial contraction W = T x_2 U_2)")
     ap.add_argument("--plain-models", type=int, default=10)
     ap.add_argument("--cpu-models", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
-                    help="c2: the benchmark workload (default); c3/c4: the uneven-batch and "
-                         "split-precision workloads, for kernel measurements")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+                    help="c2: the benchmark workload (default); c3/c4/c5: the uneven-batch, "
+                         "split-precision and refinement workloads")
     ap.add_argument("--precision", default=None, choices=["fp64", "bf16x3", "bf16x6"])
     ap.add_argument("--protocol", default="fixed", choices=["fixed", "application"],
                     help="fixed: every model runs --sweeps sweeps (the paper's timing "
@@ -150,10 +155,11 @@ PROF_SWEEPS = 10
 
 
 def measured_traffic(workload, prec_name, desc):
-    """HBM bytes per MTTKRP launch from the committed rocprofv3 counter runs
-    (FETCH_SIZE and WRITE_SIZE, calibrated with a copy kernel), or None when
-    there is no such record for this workload or when the kernel source or
-    the tiling has changed since the counters were taken."""
+    """HBM bytes per fused MTTKRP launch with its split-K reduction, from the
+    committed rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE, calibrated
+    with a copy kernel), or None when there is no such record for this
+    workload or when a kernel source or the tiling has changed since the
+    counters were taken."""
     path = os.path.join(ROOT, "profiles", "k_mttkrp_f64_%s_traffic.md" % workload)
     if prec_name != "fp64" or not os.path.exists(path):
         return None
@@ -163,9 +169,14 @@ def measured_traffic(workload, prec_name, desc):
             k, v = line.split(":", 1)
             rec[k.strip()] = v.strip()
     try:
-        src = open(os.path.join(ROOT, rec["kernel_source"]), "rb").read()
-        if hashlib.sha256(src).hexdigest() != rec["kernel_source_sha256"]:
+        paths = [x.strip() for x in rec["kernel_source"].split(";")]
+        hashes = [x.strip() for x in rec["kernel_source_sha256"].split(";")]
+        if len(paths) != len(hashes):
             return None
+        for path, h in zip(paths, hashes):
+            src = open(os.path.join(ROOT, path), "rb").read()
+            if hashlib.sha256(src).hexdigest() != h:
+                return None
         if [t.strip() for t in rec["tiling"].split(";")] != list(desc):
             return None
         return int(rec["traffic_bytes_per_launch"])
@@ -191,6 +202,7 @@ def main():
     torch.cuda.set_device(0)
     if args.efficiency_sweep:
         return efficiency_sweep()
+    refine_steps = 0
     if args.workload == "c2" and args.delete_d > 1:
         wl = synth.config2(delete_d=args.delete_d)
         desc_w = ("c2: 100x200x200 f64 fluorescence-like tensor, rank 5, 2%%%% noise; "
@@ -208,19 +220,30 @@ def main():
         desc_w = ("c3: 300x250x200 f64 rank-8 tensor; ranks 1..10 x 5 inits x 300 leave-one-out "
                   "= 15000 submodels (C = 82500); %d ALS sweeps")
         prec_name = args.precision or "fp64"
-    else:
+    elif args.workload == "c4":
         wl = synth.config4()
         desc_w = ("c4: 200x120x100x80 f64 rank-12 tensor, 1%% noise; 200 leave-one-out submodels "
                   "of rank 12; split-precision MTTKRP; %d ALS sweeps")
-        prec_name = args.precision or "bf16x3"
+        # the six-product split is the one that holds the 1e-5 gate
+        prec_name = args.precision or "bf16x6"
+    else:
+        wl = synth.config5()
+        refine_steps = 200
+        if args.sweeps == 100:
+            args.sweeps = 20
+        desc_w = ("c5: 100x150x150 rank-10 tensor stored as f32; 100 leave-one-out submodels of "
+                  "rank 10; %d ALS sweeps + " + "%d gradient-refinement steps" % refine_steps)
+        prec_name = args.precision or "fp64"
     precision = {"fp64": jk.JKC_FP64, "bf16x3": jk.JKC_SPLIT_BF16X3,
                  "bf16x6": jk.JKC_SPLIT_BF16X6}[prec_name]
     K, C, P = wl.K, wl.C, int(np.prod(wl.dims))
     N = len(wl.dims)
     sweeps = args.sweeps
-    if args.workload != "c2":
+    if args.workload in ("c3", "c5"):
         args.no_plain = True
         args.no_cpu = True
+    if args.workload == "c4":
+        args.no_plain = True
     T = jk.to_device_tensor(wl.T)
     init = [torch.from_numpy(np.ascontiguousarray(u)).cuda() for u in wl.init]
     torch.cuda.synchronize()
@@ -257,9 +280,9 @@ def main():
     # sweeps run untimed (the stamps cost about 5 % of a sweep)
     prof_sweeps = min(PROF_SWEEPS, sweeps)
 
-    def step(profile=False):
+    def step(profile=False, tree=True):
         ctx = jk.JkCals(T, wl.dims, 0, wl.ranks, wl.left_out, init, precision=precision)
-        if args.no_tree and ctx.describe(N):
+        if not tree and ctx.describe(N):
             ctx.set_mttkrp_tree(False)
         if profile:
             ctx.profile(True)
@@ -269,38 +292,112 @@ def main():
                 ctx.sweep(sweeps - prof_sweeps)
         else:
             ctx.sweep(sweeps)
+        if refine_steps:
+            ctx.refine(refine_steps)
         return ctx
 
     if args.protocol == "application":
         return application_protocol(args, wl, T, init, precision, desc_w, prec_name)
 
-    print("[bench] warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        c = step()
-        del c
-    torch.cuda.synchronize()
+    def timed(tree):
+        """Warm-up, then args.steps timed steps; (seconds, launches per
+        profiling slot, milliseconds per slot, last context)."""
+        for _ in range(args.warmup):
+            c = step(tree=tree)
+            del c
+        torch.cuda.synchronize()
+        launches = np.zeros(N + 1, np.int64)
+        kms = np.zeros(N + 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            c = step(profile=True, tree=tree)
+            n_, ms_ = c.profile_read()          # synchronises this step's stream
+            launches += n_
+            kms += ms_
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, launches, kms, c
 
-    print("[bench] timing %d steps" % args.steps, file=sys.stderr, flush=True)
-    launches = np.zeros(N, np.int64)
-    kms = np.zeros(N)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        c = step(profile=True)
-        n_, ms_ = c.profile_read()          # synchronises this step's stream
-        launches += n_
-        kms += ms_
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sec = t1 - t0
+    default_tree = not args.no_tree
+    print("[bench] %d warmup + %d timed steps (default evaluation)" % (args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+    sec, launches, kms, c = timed(default_tree)
     ms_per_step = 1000.0 * sec / args.steps
     value = K * args.steps / sec
+    has_tree = bool(c.describe(N))
 
     # fit quality and tilings of the last step (not timed)
     fit = c.get_status()[1].cpu().numpy()
     desc = [c.describe(n) for n in range(N)]
-    if c.describe(N):
+    if has_tree:
         desc.append(c.describe(N))
+    fused = {"launches": launches, "ms": kms, "sec": sec}
+    alg3 = None
+    if has_tree:
+        # the same jackknife with the fused MTTKRP of Alg. 3 on every mode
+        print("[bench] %d timed steps, fused MTTKRP on every mode" % args.steps, file=sys.stderr,
+              flush=True)
+        sec3, launches3, kms3, c3 = timed(False)
+        del c3
+        fused = {"launches": launches3, "ms": kms3, "sec": sec3}
+        alg3 = {"value": round(K * args.steps / sec3, 2), "unit": "submodels/s",
+                "ms_per_step": round(1000.0 * sec3 / args.steps, 3),
+                "note": "Alg. 3 as printed: the fused MTTKRP of every mode (no shared contraction)"}
+
+    flops_per_launch = 2.0 * C * P          # fused MTTKRP of one mode (Sec. 4.2)
+    fl, fm = fused["launches"][:N], fused["ms"][:N]
+    per_mode_ms = [float(fm[n] / fl[n]) if fl[n] else None for n in range(N)]
+    avg_ms = float(fm.sum() / max(fl.sum(), 1))
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    if precision == jk.JKC_FP64:
+        peak, kname, issued = PEAK_FP64_TFLOPS, "k_mttkrp_f64 + k_reduce", 1.0
+    else:
+        # bf16 matrix peak, counting the bf16 flops actually issued
+        issued = 3.0 if precision == jk.JKC_SPLIT_BF16X3 else 6.0
+        peak, kname = PEAK_BF16_TFLOPS, "k_mttkrp_bf + k_reduce"
+    roofline = {"bound": "mfma", "achieved": round(achieved * issued, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved * issued / peak, 4),
+                "traffic": measured_traffic(args.workload, prec_name, desc[:N]),
+                "kernel": kname + " (the fused concurrent MTTKRP of Alg. 3 with its split-K "
+                                  "reduction, every mode)",
+                "avg_launch_ms": round(avg_ms, 5),
+                "per_mode_avg_ms": [None if x is None else round(x, 5) for x in per_mode_ms],
+                "timed_launches": "HIP events stamped by the MTTKRP dispatch (start) and its "
+                                  "reduction's dispatch (stop), first %d sweeps of every timed step"
+                                  % prof_sweeps + ("" if alg3 is None else
+                                                   " of the alg3_fused_per_mode leg"),
+                "flops_per_launch": flops_per_launch * issued}
+    # MTTKRP TFLOP/s as defined for the metric: 2 C P N per sweep over the
+    # summed MTTKRP time with its reduction
+    sweep_ms = float(sum(x for x in per_mode_ms if x is not None))
+    out = {"metric": "jackknife submodels fitted/sec (JK-CALS, %d sweeps each%s)"
+                     % (sweeps, "" if not refine_steps else " + %d refinement steps" % refine_steps),
+           "value": round(value, 2), "unit": "submodels/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if precision == jk.JKC_FP64 else "bf16x%d+f32acc+f64" % (3 if precision == 1 else 6),
+           "data": "synthetic",
+           "config": {"workload": desc_w % sweeps, "dims": list(wl.dims), "models": K,
+                      "columns": C, "sweeps": sweeps, "precision": prec_name,
+                      "delete_d": int(wl.left_out.shape[1]) if wl.left_out.ndim == 2 else 1,
+                      "fused_flop_overhead": round(wl.dims[0] / (wl.dims[0] - (
+                          int(wl.left_out.shape[1]) if wl.left_out.ndim == 2 else 1)), 5),
+                      "evaluation": "shared partial contraction W = T x_2 U_2 for modes 0 and 1, "
+                                    "fused MTTKRP for mode 2" if has_tree else
+                                    "fused MTTKRP on every mode (Alg. 3)",
+                      "tiling": tiling or desc},
+           "mttkrp_tflops": round(N * flops_per_launch / (sweep_ms * 1e-3) / 1e12, 3) if sweep_ms else None,
+           "roofline": roofline}
+    if alg3 is not None:
+        out["alg3_fused_per_mode"] = alg3
+    if has_tree and launches[N]:
+        w_ms = float(kms[N] / launches[N])
+        w_tf = flops_per_launch / (w_ms * 1e-3) / 1e12
+        out["tree_w"] = {"kernel": "k_mttkrp_f64 on the two-way view of T (W = T x_2 U_2, no "
+                                   "Khatri-Rao products, no split-K)",
+                         "avg_launch_ms": round(w_ms, 5), "achieved": round(w_tf, 3),
+                         "frac": round(w_tf / PEAK_FP64_TFLOPS, 4), "launches_per_sweep": 1}
+
     # after the timed region: the MTTKRP with its split-K reduction (what a
     # caller of jk_cals_mttkrp gets), per mode, HIP events on the stream
     mout = torch.empty((max(wl.dims), C), dtype=torch.float64, device="cuda")
@@ -314,6 +411,11 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         with_reduce_ms.append(e0.elapsed_time(e1) / 5)
+    out["mttkrp_call"] = {
+        "per_mode_ms": [round(x, 5) for x in with_reduce_ms],
+        "tflops": round(flops_per_launch * issued / (float(np.mean(with_reduce_ms)) * 1e-3) / 1e12, 3),
+        "note": "jk_cals_mttkrp (MTTKRP, reduction and copy-out into a caller buffer), "
+                "torch events around 5 calls"}
     # jackknife post-processing (Alg. 2: matching, scale adjustment and the
     # standard deviations) of one set of fitted submodels: the leave-one-out
     # run after the first model, against the full model when there is one
@@ -345,49 +447,10 @@ def main():
         torch.cuda.synchronize()
         del ci
     init_ms = 1000.0 * (time.perf_counter() - t_i) / 3
-
-    flops_per_launch = 2.0 * C * P          # fused MTTKRP of one mode (Sec. 4.2)
-    avg_ms = float(kms.sum() / max(launches.sum(), 1))
-    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
-    if precision == jk.JKC_FP64:
-        peak, kname, issued = PEAK_FP64_TFLOPS, "k_mttkrp_f64", 1.0
-    else:
-        # bf16 matrix peak, counting the bf16 flops actually issued
-        issued = 3.0 if precision == jk.JKC_SPLIT_BF16X3 else 6.0
-        peak, kname = PEAK_BF16_TFLOPS, "k_mttkrp_split"
-    roofline = {"bound": "mfma", "achieved": round(achieved * issued, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved * issued / peak, 4),
-                "traffic": measured_traffic(args.workload, prec_name, desc),
-                "kernel": kname, "avg_launch_ms": round(avg_ms, 5),
-                "per_mode_avg_ms": [round(float(kms[n] / max(launches[n], 1)), 5) for n in range(N)],
-                "timed_launches": (("per sweep: the shared contraction W = T x_2 U_2 (counted under mode 0; "
-                                    "modes 0 and 1 read W) and the fused MTTKRP of mode 2"
-                                    if any(d.startswith("tree") for d in desc) else
-                                    "per sweep: the fused MTTKRP of every mode") +
-                                   "; events on the first %d sweeps of every timed step" % prof_sweeps),
-                "flops_per_launch": flops_per_launch * issued}
-
-    out = {"metric": "jackknife submodels fitted/sec (JK-CALS, %d sweeps each)" % sweeps,
-           "value": round(value, 2), "unit": "submodels/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64" if precision == jk.JKC_FP64 else "bf16x%d+f32acc+f64" % (3 if precision == 1 else 6),
-           "data": "synthetic",
-           "config": {"workload": desc_w % sweeps, "dims": list(wl.dims), "models": K,
-                      "columns": C, "sweeps": sweeps, "precision": prec_name,
-                      "delete_d": int(wl.left_out.shape[1]) if wl.left_out.ndim == 2 else 1,
-                      "fused_flop_overhead": round(wl.dims[0] / (wl.dims[0] - (
-                          int(wl.left_out.shape[1]) if wl.left_out.ndim == 2 else 1)), 5),
-                      "tiling": tiling or desc},
-           "mttkrp_tflops": round(achieved, 3),
-           "roofline": roofline,
-           "init_ms": round(init_ms, 3),
-           "mttkrp_with_reduce": {
-               "per_mode_ms": [round(x, 5) for x in with_reduce_ms],
-               "tflops": round(flops_per_launch / (float(np.mean(with_reduce_ms)) * 1e-3) / 1e12, 3)},
-           "fit_range": [round(float(fit.min()), 6), round(float(fit.max()), 6)],
-           "jackknife_postprocess": {"ms": None if jk_ms is None else round(jk_ms, 4),
-                                     "reference_model": ref, "submodels": cnt}}
+    out["init_ms"] = round(init_ms, 3)
+    out["fit_range"] = [round(float(fit.min()), 6), round(float(fit.max()), 6)]
+    out["jackknife_postprocess"] = {"ms": None if jk_ms is None else round(jk_ms, 4),
+                                    "reference_model": ref, "submodels": cnt}
 
     if not args.no_plain:
         print("[bench] plain per-submodel ALS on the GPU (%d models)" % args.plain_models,
@@ -425,30 +488,83 @@ def main():
                                 "speedup_jk_cals": round(value / plain_rate, 2)}
 
     if not args.no_cpu:
-        print("[bench] CPU oracle on a sample", file=sys.stderr, flush=True)
-        import oracle
-        from threadpoolctl import threadpool_info, threadpool_limits
-        cores = min(16, os.cpu_count() or 1)
-        n_cpu = min(args.cpu_models, K)
-        Th = np.asarray(wl.T)
-        runs = []
-        # one thread and all (up to 16) threads: small per-model BLAS calls
-        # often run faster on one thread; the faster run is the baseline
-        for lim in (1, cores):
-            with threadpool_limits(limits=lim):
-                used = 1 if lim == 1 else max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-                t0 = time.perf_counter()
-                oracle.jk_als(Th, 0, wl.ranks, wl.left_out, wl.init, sweeps, models=list(range(n_cpu)))
-                tc = time.perf_counter() - t0
-            runs.append({"value": round(n_cpu / tc, 4), "unit": "submodels/s", "cores": int(used),
-                         "kind": "oracle",
-                         "sample": "%d of %d submodels x %d sweeps, numpy float64 per-submodel ALS"
-                                   % (n_cpu, K, sweeps)})
-        runs.sort(key=lambda r: -r["value"])
-        out["cpu_baseline"] = runs[0]
-        out["cpu_baseline_other_threads"] = runs[1]
+        out.update(cpu_baseline(args, wl, T, init, precision, sweeps))
     print(json.dumps(out))
     return 0
+
+
+def cpu_baseline(args, wl, T, init, precision, sweeps):
+    """The oracle (per-submodel float64 ALS on the reduced tensor) timed on
+    the host on a bounded sample, at one thread and at up to sixteen; the
+    faster run is the baseline.  For the split-precision workload the sample
+    is one model for one sweep, and the GPU's result for that model is
+    compared with it (every result's error stated)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2112_03985_amd as jk
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    print("[bench] CPU oracle on a sample", file=sys.stderr, flush=True)
+    cores = min(16, os.cpu_count() or 1)
+    split = precision != jk.JKC_FP64
+    n_cpu = 1 if split else min(args.cpu_models, wl.K)
+    n_sweeps = 1 if split else sweeps
+    Th = np.asarray(wl.T)
+    runs = []
+    res = None
+    for lim in (1, cores):
+        with threadpool_limits(limits=lim):
+            used = 1 if lim == 1 else max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+            t0 = time.perf_counter()
+            res = oracle.jk_als(Th, 0, wl.ranks, wl.left_out, wl.init, n_sweeps,
+                                models=list(range(n_cpu)), record_factors=[n_sweeps] if split else ())
+            tc = time.perf_counter() - t0
+        runs.append({"value": round(n_cpu * n_sweeps / sweeps / tc, 4), "unit": "submodels/s",
+                     "cores": int(used), "kind": "oracle",
+                     "sample": "%d of %d submodels x %d sweeps (scaled to %d sweeps per submodel), "
+                               "numpy float64 per-submodel ALS" % (n_cpu, wl.K, n_sweeps, sweeps)})
+    runs.sort(key=lambda r: -r["value"])
+    out = {"cpu_baseline": runs[0], "cpu_baseline_other_threads": runs[1]}
+    if split:
+        # the GPU's split-precision run of the same sample: one sweep from
+        # the same init, every result against the oracle's
+        ctx = jk.JkCals(T, wl.dims, 0, wl.ranks, wl.left_out, init, precision=precision)
+        Ms = [ctx.mttkrp(n).cpu().numpy() for n in range(len(wl.dims))]
+        ctx.sweep(1)
+        err = ctx.get_status()[0].cpu().numpy()
+        facs = [ctx.get_factors(n) for n in range(len(wl.dims))]
+        r = res[0]
+        R = int(wl.ranks[0])
+        Up = r.padded(r.U_hist[1])
+
+        def rel(a, b):
+            nb = np.linalg.norm(b)
+            return float(np.linalg.norm(a - b) / nb), float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+        # the init MTTKRP of model 0 by definition (reduced tensor, reduced
+        # factors), padded with the left-out row
+        p = int(wl.left_out[0])
+        U0 = [np.array(u[:, :R]) for u in wl.init]
+        U0[0] = oracle.reduce_init(U0[0], p)
+        Tk = oracle.reduce_tensor(Th, 0, p)
+        mt = []
+        for n in range(len(wl.dims)):
+            M = oracle.mttkrp(Tk, U0, n)
+            if n == 0:
+                M = np.insert(M, p, 0.0, axis=0)
+            mt.append(rel(Ms[n][:, :R], M))
+        out["split_error_vs_oracle"] = {
+            "model": 0, "gate": 1e-5,
+            "mttkrp_at_init": [{"normwise": round(a, 9), "elementwise": round(b, 9)} for a, b in mt],
+            "factors_after_one_sweep": [
+                dict(zip(("normwise", "elementwise"), (round(x, 9) for x in
+                                                        rel(facs[n][0].cpu().numpy()[:, :R], Up[n]))))
+                for n in range(len(wl.dims))],
+            "lambda_after_one_sweep": round(rel(facs[0][1].cpu().numpy()[:R], r.lam_hist[0])[0], 9),
+            "error_after_one_sweep": round(abs(float(err[0]) - r.e_hist[0]) / r.normT2, 9)}
+    return out
 
 
 if __name__ == "__main__":

@@ -190,6 +190,16 @@ jkc_status jk_cals_loss_grad(jkc_ctx *ctx, double *loss);
 jkc_status jk_cals_get_grad(jkc_ctx *ctx, int32_t mode, const double *weights,
                             double *out);
 
+/* out(i, c) = weights[k] * src(i, c) for every column c of model k: the
+ * chain rule of a loss that weights model k's CP loss by weights[k] (the
+ * backward of the per-model loss; Sec. 2 cites gradient-based CP), applied to
+ * gradients a caller copied out with jk_cals_get_grad(..., NULL, ...).
+ * src, out: device rows x C row-major (src == out allowed); weights: device
+ * [K] or NULL (all ones).  EINVAL for rows < 0 or NULL buffers when rows > 0.
+ * Asynchronous on the context's stream. */
+jkc_status jk_cals_scale_columns(jkc_ctx *ctx, int32_t rows, const double *src,
+                                 const double *weights, double *out);
+
 /* Gradient refinement: fold lambda into the last factor, fix the step
  * eta_k = 1 / sum_n ||H_n^(k)||_F from the current factors, then take
  * `steps` steps U_n <- U_n - eta_k dF/dU_n (all modes at once).  If loss is
@@ -260,9 +270,12 @@ const char *jk_cals_describe(jkc_ctx *ctx, int32_t mode);
  * Host only. */
 jkc_status jk_cals_set_update_kernel(jkc_ctx *ctx, int32_t which);
 
-/* Shared partial contraction of a 3-way float64 sweep (Sec. 3: the MTTKRPs
- * of Alg. 1 inside the concurrent sweep, evaluated as a two-level dimension
- * tree; modes numbered from 0): at mode 0 the tensor is contracted once with
+/* Shared partial contraction of a 3-way float64 sweep: an extension beyond
+ * Alg. 3, which computes every mode's MTTKRP separately.  The MTTKRPs of
+ * Alg. 1 inside the concurrent sweep are evaluated as a two-level dimension
+ * tree (the reuse of partial MTTKRPs of Phan et al., the paper's reference
+ * for the error identity; modes numbered from 0): at mode 0 the tensor is
+ * contracted once with
  * the last factor, W(i,j,c) = sum_k T(i,j,k) U_2(k,c) for all active
  * columns, and M_0 = sum_j W U_1, M_1 = sum_i W U_0 (U_0 just updated) are
  * read from W; mode 2 keeps the fused MTTKRP.  The results equal the fused
@@ -295,15 +308,20 @@ int32_t jk_cals_num_tilings(jkc_ctx *ctx);
  * a multi-factor takes 2^31 bytes or more.  Host only. */
 jkc_status jk_cals_set_tiling(jkc_ctx *ctx, int32_t mode, int32_t variant, int32_t splits);
 
-/* Kernel timing of the fused MTTKRP (the dominant kernel): while enabled,
- * every MTTKRP launch of this context is bracketed by a pair of HIP events on
- * the context's stream (at most 65536 launches are kept).  Host only. */
+/* Kernel timing of the fused MTTKRP (the dominant kernel; Alg. 3, MTTKRP
+ * step): while enabled, every MTTKRP launch of this context is bracketed by a
+ * pair of HIP events on the context's stream, stamped by the dispatches
+ * themselves (at most 65536 launches are kept).  A launch whose split-K
+ * partials are summed by a separate reduction is timed from the start of the
+ * MTTKRP to the end of that reduction; the shared contraction W of 3-way
+ * sweeps is timed on its own.  Host only. */
 jkc_status jk_cals_profile(jkc_ctx *ctx, int32_t enable);
 
-/* Synchronise the stream, then report per mode the number of MTTKRP launches
- * timed since the last read and their summed kernel time in milliseconds
- * (launches: host [N] int64, ms: host [N] float64; either may be NULL).
- * Resets the counts. */
+/* Synchronise the stream, then report per slot the number of launches timed
+ * since the last read and their summed time in milliseconds: slot n < N is
+ * the fused MTTKRP of mode n (with its reduction, as above), slot N the
+ * shared contraction W (launches: host [N+1] int64, ms: host [N+1] float64;
+ * either may be NULL).  Resets the counts. */
 jkc_status jk_cals_profile_read(jkc_ctx *ctx, int64_t *launches, double *ms);
 
 /* Explicit slice removal of Alg. 2: out = T with slice p of the sampled mode

@@ -87,6 +87,7 @@ def lib() -> ctypes.CDLL:
         "jk_cals_get_status": (I32, [VP, VP, VP, VP, VP]),
         "jk_cals_loss_grad": (I32, [VP, VP]),
         "jk_cals_get_grad": (I32, [VP, I32, VP, VP]),
+        "jk_cals_scale_columns": (I32, [VP, I32, VP, VP, VP]),
         "jk_cals_refine": (I32, [VP, I32, VP]),
         "jk_cals_tune": (I32, [VP, I32]),
         "jk_cals_describe": (ctypes.c_char_p, [VP, I32]),
@@ -131,6 +132,31 @@ def _stream(stream=None) -> int:
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return int(s.cuda_stream)
+
+
+def _check_buffer(t, shape, name, dtype="float64", device=None, allow_none=False):
+    """Validate a caller buffer before its pointer reaches the library: a
+    contiguous device tensor of the given dtype and shape (and device).
+    Raises TypeError (dtype, not a tensor) or ValueError (placement, shape,
+    layout); nothing is launched."""
+    import torch
+    if t is None:
+        if allow_none:
+            return
+        raise ValueError("%s is required" % name)
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    want = {"float64": torch.float64, "int32": torch.int32}[dtype]
+    if t.dtype != want:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if tuple(t.shape) != tuple(int(x) for x in shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if device is not None and t.device != device:
+        raise ValueError("%s is on %s, the context on %s" % (name, t.device, device))
 
 
 def to_device_tensor(T: np.ndarray, device="cuda"):
@@ -240,12 +266,21 @@ class JkCals:
         import torch
         return torch.empty((rows, cols), dtype=torch.float64, device=self.device)
 
+    def _mode(self, mode):
+        if not 0 <= int(mode) < self.N:
+            raise ValueError("mode must be in 0..%d" % (self.N - 1))
+        return int(mode)
+
     def mttkrp(self, mode: int, out=None):
-        out = self._out(self.dims[mode], self.C) if out is None else out
-        _check(lib().jk_cals_mttkrp(self.ctx, int(mode), ctypes.c_void_p(_ptr(out))))
+        mode = self._mode(mode)
+        if out is None:
+            out = self._out(self.dims[mode], self.C)
+        _check_buffer(out, (self.dims[mode], self.C), "out", device=self.device)
+        _check(lib().jk_cals_mttkrp(self.ctx, mode, ctypes.c_void_p(_ptr(out))))
         return out
 
     def sweep(self, nsweeps: int = 1, fit=None):
+        _check_buffer(fit, (self.K,), "fit", device=self.device, allow_none=True)
         _check(lib().jk_cals_sweep(self.ctx, int(nsweeps), ctypes.c_void_p(_ptr(fit))))
         return fit
 
@@ -268,7 +303,10 @@ class JkCals:
         return (out, lam) if with_lambda else out
 
     def set_factors(self, mode: int, U, lam=None):
-        _check(lib().jk_cals_set_factors(self.ctx, int(mode), ctypes.c_void_p(_ptr(U)),
+        mode = self._mode(mode)
+        _check_buffer(lam, (self.C,), "lambda", device=self.device, allow_none=True)
+        _check_buffer(U, (self.dims[mode], self.C), "U", device=self.device)
+        _check(lib().jk_cals_set_factors(self.ctx, mode, ctypes.c_void_p(_ptr(U)),
                                          ctypes.c_void_p(_ptr(lam))))
 
     def get_status(self):
@@ -282,16 +320,37 @@ class JkCals:
         return err, fit, st, it
 
     def loss_grad(self, loss=None):
+        _check_buffer(loss, (self.K,), "loss", device=self.device, allow_none=True)
         _check(lib().jk_cals_loss_grad(self.ctx, ctypes.c_void_p(_ptr(loss))))
         return loss
 
     def get_grad(self, mode: int, weights=None, out=None):
-        out = self._out(self.dims[mode], self.C) if out is None else out
-        _check(lib().jk_cals_get_grad(self.ctx, int(mode), ctypes.c_void_p(_ptr(weights)),
+        mode = self._mode(mode)
+        if out is None:
+            out = self._out(self.dims[mode], self.C)
+        _check_buffer(out, (self.dims[mode], self.C), "out", device=self.device)
+        _check_buffer(weights, (self.K,), "weights", device=self.device, allow_none=True)
+        _check(lib().jk_cals_get_grad(self.ctx, mode, ctypes.c_void_p(_ptr(weights)),
                                       ctypes.c_void_p(_ptr(out))))
         return out
 
+    def scale_columns(self, src, weights=None, out=None):
+        """out(i, c) = weights[model of c] * src(i, c) for a (rows, C) block."""
+        if src is None or getattr(src, "dim", lambda: 0)() != 2:
+            raise ValueError("src must be a (rows, C) device tensor")
+        rows = int(src.shape[0])
+        _check_buffer(src, (rows, self.C), "src", device=self.device)
+        if out is None:
+            out = self._out(rows, self.C)
+        _check_buffer(out, (rows, self.C), "out", device=self.device)
+        _check_buffer(weights, (self.K,), "weights", device=self.device, allow_none=True)
+        _check(lib().jk_cals_scale_columns(self.ctx, rows, ctypes.c_void_p(_ptr(src)),
+                                           ctypes.c_void_p(_ptr(weights)),
+                                           ctypes.c_void_p(_ptr(out))))
+        return out
+
     def refine(self, steps: int, loss=None):
+        _check_buffer(loss, (self.K,), "loss", device=self.device, allow_none=True)
         _check(lib().jk_cals_refine(self.ctx, int(steps), ctypes.c_void_p(_ptr(loss))))
         return loss
 
@@ -323,9 +382,11 @@ class JkCals:
         _check(lib().jk_cals_profile(self.ctx, 1 if enable else 0))
 
     def profile_read(self):
-        """(launches per mode, kernel milliseconds per mode) since last read."""
-        n = np.zeros(self.N, np.int64)
-        ms = np.zeros(self.N, np.float64)
+        """(launches, milliseconds) per slot since the last read: slot n < N
+        the fused MTTKRP of mode n with its split-K reduction, slot N the
+        shared contraction W."""
+        n = np.zeros(self.N + 1, np.int64)
+        ms = np.zeros(self.N + 1, np.float64)
         _check(lib().jk_cals_profile_read(self.ctx, n.ctypes.data_as(ctypes.c_void_p),
                                           ms.ctypes.data_as(ctypes.c_void_p)))
         return n, ms
@@ -386,6 +447,10 @@ def jk_cals_get_grad(ctx: JkCals, mode: int, weights=None, out=None):
     return ctx.get_grad(mode, weights, out)
 
 
+def jk_cals_scale_columns(ctx: JkCals, src, weights=None, out=None):
+    return ctx.scale_columns(src, weights, out)
+
+
 def jk_cals_refine(ctx: JkCals, steps: int, loss=None):
     return ctx.refine(steps, loss)
 
@@ -437,9 +502,17 @@ def jk_cals_remove_slice(tensor, dims, sampled_mode, p, out=None, stream=None):
     if tensor.dtype not in (torch.float64, torch.float32):
         raise TypeError("tensor must be float64 or float32")
     tdt = JKC_TENSOR_F64 if tensor.dtype == torch.float64 else JKC_TENSOR_F32
+    if not tensor.is_cuda or not tensor.is_contiguous():
+        raise ValueError("tensor must be a contiguous device tensor")
+    if tensor.numel() != int(np.prod(dims)):
+        raise ValueError("tensor has %d elements, dims say %d" % (tensor.numel(), int(np.prod(dims))))
     n_out = int(np.prod(dims)) // int(dims[sampled_mode]) * (int(dims[sampled_mode]) - 1)
     if out is None:
         out = torch.empty(n_out, dtype=tensor.dtype, device=tensor.device)
+    if (not isinstance(out, torch.Tensor) or out.dtype != tensor.dtype or not out.is_cuda
+            or out.numel() != n_out or not out.is_contiguous()):
+        raise ValueError("out must be a contiguous device tensor of %d elements of the tensor's dtype"
+                         % n_out)
     prob, keep = make_problem(dims, sampled_mode, [1], [-1], tdt, JKC_FP64, 1, _stream(stream))
     _check(lib().jk_cals_remove_slice(ctypes.byref(prob), ctypes.c_void_p(tensor.data_ptr()),
                                       int(p), ctypes.c_void_p(out.data_ptr())))
@@ -464,9 +537,12 @@ def _make_loss_function():
         forward(ctx, U_0, ..., U_{N-1}) -> loss[K]: installs the factors
         (device (I_n, C) float64; row p_k of the sampled mode is taken as 0)
         and runs the all-mode fused MTTKRP, the loss and the gradients in the
-        library.  backward(grad_loss[K]) returns grad_loss[k] * dF_k/dU_n on
-        model k's columns, computed by the library from the cached
-        gradients."""
+        library; the unweighted gradients are copied out of the context
+        right away and saved with the graph node, so later calls on the same
+        context (another forward, loss_grad, refine) cannot change what this
+        node's backward returns.  backward(grad_loss[K]) returns
+        grad_loss[k] * dF_k/dU_n on model k's columns (the library scales
+        the saved gradients)."""
 
         @staticmethod
         def forward(fctx, jkctx, *factors):
@@ -478,13 +554,14 @@ def _make_loss_function():
             loss = torch.empty(jkctx.K, dtype=torch.float64, device=jkctx.device)
             jkctx.loss_grad(loss)
             fctx.jk = jkctx
+            fctx.grads = [jkctx.get_grad(n) for n in range(jkctx.N)]
             return loss
 
         @staticmethod
         def backward(fctx, grad_loss):
             jkctx = fctx.jk
             w = grad_loss.detach().to(torch.float64).contiguous()
-            grads = [jkctx.get_grad(n, weights=w) for n in range(jkctx.N)]
+            grads = [jkctx.scale_columns(g, weights=w) for g in fctx.grads]
             return (None, *grads)
 
     return JKCPLoss

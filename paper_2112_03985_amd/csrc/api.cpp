@@ -221,8 +221,9 @@ jkc_status make_plan(const jkc_problem* prob, Plan* pl) {
           std::max(pl->partial_doubles, (int64_t)pl->split_max[n] * pl->dims[n] * pl->ldc);
   }
   // W = T x_2 U_2 for 3-way float64 problems, when it takes at most
-  // tree_max_gib GiB of the workspace (default 64; its rows i + I_0 j; the
-  // pass kernel's grid covers up to 131070 rows of each mode)
+  // tree_max_gib GiB of the workspace (default 64; its rows i + I_0 j, fewer
+  // than 2^31 of them: 32-bit row index in the kernel), with I_0, I_1 at
+  // most 100000
   pl->tree_rows = 0;
   const int64_t tree_cap = prob->tree_max_gib == 0 ? (int64_t(64) << 30)
                            : prob->tree_max_gib < 0 ? -1
@@ -437,11 +438,14 @@ const std::vector<MttkrpVariant>& variants_for(const jkc_ctx* ctx) {
   return mttkrp_f64_variants();
 }
 
-jkc_status launch_mttkrp_timed(jkc_ctx* ctx, const MttkrpArgs& a, const Tiling& t, int pmode);
+jkc_status launch_mttkrp_timed(jkc_ctx* ctx, const MttkrpArgs& a, const Tiling& t, int slot,
+                               bool reduce_follows);
 
 // Enqueue the fused MTTKRP of mode n.  Result: split-K partials in
-// ctx->partial (t.splits > 1) or the product itself in ctx->Mbuf.
-jkc_status enqueue_mttkrp(jkc_ctx* ctx, int n, const Tiling& t) {
+// ctx->partial (t.splits > 1) or the product itself in ctx->Mbuf.  When
+// reduce_follows, the reduction launched next (launch_reduce_timed) closes
+// the launch's timing window.
+jkc_status enqueue_mttkrp(jkc_ctx* ctx, int n, const Tiling& t, bool reduce_follows = false) {
   const auto& vars = variants_for(ctx);
   if (t.variant < 0 || t.variant >= (int)vars.size()) return fail(JKC_ESTATE, "no tiling");
   MttkrpArgs a{};
@@ -492,13 +496,18 @@ jkc_status enqueue_mttkrp(jkc_ctx* ctx, int n, const Tiling& t) {
   } else {
     a.partial = ctx->Mbuf;
   }
-  return launch_mttkrp_timed(ctx, a, t, n);
+  return launch_mttkrp_timed(ctx, a, t, n, reduce_follows);
 }
 
-// Launch a filled MTTKRP, timed under mode pmode while jk_cals_profile is on.
-jkc_status launch_mttkrp_timed(jkc_ctx* ctx, const MttkrpArgs& a, const Tiling& t, int pmode) {
+// Launch a filled MTTKRP, timed in profiling slot `slot` while
+// jk_cals_profile is on (slots 0..N-1: the fused MTTKRP of that mode with
+// its split-K reduction; slot N: the shared contraction W).  The dispatch
+// stamps the start event; the stop event is stamped by this dispatch, or,
+// when reduce_follows, by the reduction's.
+jkc_status launch_mttkrp_timed(jkc_ctx* ctx, const MttkrpArgs& a, const Tiling& t, int slot,
+                               bool reduce_follows) {
   const auto& vars = variants_for(ctx);
-  const int n = pmode;
+  const int n = slot;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (ctx->prof_on && ctx->prof_used < kMaxTimedLaunches) {
     const size_t i = ctx->prof_used;
@@ -518,7 +527,23 @@ jkc_status launch_mttkrp_timed(jkc_ctx* ctx, const MttkrpArgs& a, const Tiling& 
     ev1 = ctx->prof_ev[2 * i + 1];
     ++ctx->prof_used;
   }
+  ctx->prof_pending_stop = nullptr;
+  if (reduce_follows) {
+    ctx->prof_pending_stop = ev1;
+    ev1 = nullptr;
+  }
   JKC_HIP(vars[t.variant].launch(a, ctx->stream, ev0, ev1));
+  return JKC_OK;
+}
+
+// The split-K reduction of the MTTKRP launched just before (stamps that
+// launch's pending stop event, if any).
+jkc_status launch_reduce_timed(jkc_ctx* ctx, const double* partial, int32_t splits, int32_t rows,
+                               int32_t ncols, int32_t zero_rows, double* out, int32_t ldo) {
+  hipEvent_t stop = ctx->prof_pending_stop;
+  ctx->prof_pending_stop = nullptr;
+  JKC_HIP(launch_reduce(partial, splits, rows, ctx->ldc, ncols, ctx->left_out(), zero_rows, out, ldo,
+                        ctx->stream, stop));
   return JKC_OK;
 }
 
@@ -532,13 +557,13 @@ int effective_splits(const jkc_ctx* ctx, int n, const Tiling& t) {
 // row removal when n is the sampled mode.
 jkc_status enqueue_mttkrp_reduced(jkc_ctx* ctx, int n, double* out, int ldo, int ncols) {
   const Tiling& t = ctx->tiling[n];
-  JKC_TRY(enqueue_mttkrp(ctx, n, t));
   const int splits = effective_splits(ctx, n, t);
+  const bool reduce = !(splits == 1 && out == ctx->Mbuf);   // else rows cleared by the consumer
+  JKC_TRY(enqueue_mttkrp(ctx, n, t, reduce));
+  if (!reduce) return JKC_OK;
   const double* src = splits > 1 ? ctx->partial : ctx->Mbuf;
-  if (splits == 1 && out == ctx->Mbuf) return JKC_OK;  // rows cleared by the consumer
-  JKC_HIP(launch_reduce(src, splits, (int32_t)ctx->dims[n], ctx->ldc, ncols, ctx->left_out(),
-                        n == ctx->nhat ? 1 : 0, out, ldo, ctx->stream));
-  return JKC_OK;
+  return launch_reduce_timed(ctx, src, splits, (int32_t)ctx->dims[n], ncols, n == ctx->nhat ? 1 : 0,
+                             out, ldo);
 }
 
 // W = T x_2 U_2 over the active columns (tree.hip explains the scheme):
@@ -571,7 +596,7 @@ jkc_status enqueue_tree_w(jkc_ctx* ctx) {
   a.kchunk = align_up(a.J, t.bk);
   a.splits = 1;
   a.partial = ctx->Wtree;
-  JKC_TRY(launch_mttkrp_timed(ctx, a, t, 0));
+  JKC_TRY(launch_mttkrp_timed(ctx, a, t, ctx->N, false));
   ctx->tree_fresh = true;
   return JKC_OK;
 }
@@ -757,7 +782,7 @@ jkc_status enqueue_loss_grad(jkc_ctx* ctx, double* loss) {
     if ((from_w || effective_splits(ctx, n, ctx->tiling[n]) == 1) && n == ctx->nhat) {
       // the direct product still carries row p: clear it through a reduce pass
       JKC_HIP(launch_reduce(ctx->Mbuf, 1, (int32_t)ctx->dims[n], ctx->ldc, ctx->ldc, ctx->left_out(),
-                            1, ctx->Mbuf, ctx->ldc, ctx->stream));
+                            1, ctx->Mbuf, ctx->ldc, ctx->stream, nullptr));
     }
     GradArgs g{};
     g.mt = ctx->table();
@@ -1003,11 +1028,11 @@ jkc_status jk_cals_mttkrp(jkc_ctx* ctx, int32_t mode, double* out) {
   JKC_TRY(check_mode(ctx, mode));
   if (!out) return fail(JKC_EINVAL, "out is NULL");
   const Tiling& t = ctx->tiling[mode];
-  JKC_TRY(enqueue_mttkrp(ctx, mode, t));
+  JKC_TRY(enqueue_mttkrp(ctx, mode, t, true));
   const int splits = effective_splits(ctx, mode, t);
-  JKC_HIP(launch_reduce(splits > 1 ? ctx->partial : ctx->Mbuf, splits, (int32_t)ctx->dims[mode],
-                        ctx->ldc, ctx->C, ctx->left_out(), mode == ctx->nhat ? 1 : 0, out, ctx->C,
-                        ctx->stream));
+  JKC_TRY(launch_reduce_timed(ctx, splits > 1 ? ctx->partial : ctx->Mbuf, splits,
+                              (int32_t)ctx->dims[mode], ctx->C, mode == ctx->nhat ? 1 : 0, out,
+                              ctx->C));
   g_last_error.clear();
   return JKC_OK;
 }
@@ -1172,7 +1197,22 @@ jkc_status jk_cals_get_grad(jkc_ctx* ctx, int32_t mode, const double* weights, d
   JKC_TRY(check_mode(ctx, mode));
   if (!out) return fail(JKC_EINVAL, "out is NULL");
   JKC_HIP(launch_scale_cols_by_model(ctx->table(), weights, ctx->grad[mode],
-                                     (int32_t)ctx->dims[mode], ctx->ldc, out, ctx->C, ctx->C,
+                                     (int32_t)ctx->dims[mode], ctx->ldc, out, ctx->C,
+                                     ctx->stream));
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_scale_columns(jkc_ctx* ctx, int32_t rows, const double* src,
+                                 const double* weights, double* out) {
+  JKC_TRY(check_ctx(ctx));
+  if (rows < 0) return fail(JKC_EINVAL, "rows must be >= 0");
+  if (rows > 0 && (!src || !out)) return fail(JKC_EINVAL, "src/out is NULL");
+  if (rows == 0) {
+    g_last_error.clear();
+    return JKC_OK;
+  }
+  JKC_HIP(launch_scale_cols_by_model(ctx->table(), weights, src, rows, ctx->C, out, ctx->C,
                                      ctx->stream));
   g_last_error.clear();
   return JKC_OK;
@@ -1293,7 +1333,7 @@ jkc_status jk_cals_tune(jkc_ctx* ctx, int32_t reps) {
           if (eff > 1)
             JKC_HIP(launch_reduce(ctx->partial, eff, (int32_t)ctx->dims[n], ctx->ldc, ctx->ldc,
                                   ctx->left_out(), n == ctx->nhat ? 1 : 0, ctx->Mbuf, ctx->ldc,
-                                  ctx->stream));
+                                  ctx->stream, nullptr));
           return JKC_OK;
         };
         result = run();
@@ -1407,8 +1447,8 @@ jkc_status jk_cals_profile(jkc_ctx* ctx, int32_t enable) {
 jkc_status jk_cals_profile_read(jkc_ctx* ctx, int64_t* launches, double* ms) {
   JKC_TRY(check_ctx(ctx));
   JKC_HIP(hipStreamSynchronize(ctx->stream));
-  std::vector<int64_t> cnt(ctx->N, 0);
-  std::vector<double> tot(ctx->N, 0.0);
+  std::vector<int64_t> cnt(ctx->N + 1, 0);
+  std::vector<double> tot(ctx->N + 1, 0.0);
   for (size_t i = 0; i < ctx->prof_used; ++i) {
     float t = 0.f;
     JKC_HIP(hipEventElapsedTime(&t, ctx->prof_ev[2 * i], ctx->prof_ev[2 * i + 1]));
@@ -1416,7 +1456,7 @@ jkc_status jk_cals_profile_read(jkc_ctx* ctx, int64_t* launches, double* ms) {
     tot[ctx->prof_mode[i]] += t;
   }
   ctx->prof_used = 0;
-  for (int n = 0; n < ctx->N; ++n) {
+  for (int n = 0; n <= ctx->N; ++n) {
     if (launches) launches[n] = cnt[n];
     if (ms) ms[n] = tot[n];
   }

@@ -164,10 +164,11 @@ struct LeftOut {
 hipError_t launch_tree_pass(const double* W, const double* F, int32_t S, int64_t ostep,
                             int64_t sstep, int32_t nout, int32_t ldc, int32_t ncols, double* out,
                             hipStream_t s);
+// (stop: when not null, an event the dispatch stamps at its end)
 hipError_t launch_reduce(const double* partial, int32_t splits, int32_t rows,
                          int32_t ldc, int32_t ncols, LeftOut lo,
                          int32_t zero_rows, double* out, int32_t ldo,
-                         hipStream_t s);
+                         hipStream_t s, hipEvent_t stop);
 
 // Preparation kernels.
 hipError_t launch_copy_tensor(const void* src, int32_t src_f32, void* dst,
@@ -215,7 +216,7 @@ hipError_t launch_grad_assemble(const GradArgs& a, hipStream_t s);
 hipError_t launch_scale_cols_by_model(const ModelTable& mt, const double* w,
                                       const double* src, int32_t rows,
                                       int32_t ldc, double* dst, int32_t ldd,
-                                      int32_t C, hipStream_t s);
+                                      hipStream_t s);
 hipError_t launch_fold_lambda(double* U, int32_t rows, int32_t ldc, int32_t C,
                               double* lambda, hipStream_t s);
 hipError_t launch_gd_eta(const ModelTable& mt, int32_t N, const double* const* G,
@@ -304,8 +305,9 @@ struct jkc_ctx {
   // MTTKRP kernel timing (jk_cals_profile)
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;     // pairs: [2i] start, [2i+1] stop
-  std::vector<int> prof_mode;          // mode of each timed pair
+  std::vector<int> prof_mode;          // slot of each timed pair (mode, or N for W)
   size_t prof_used = 0;
+  hipEvent_t prof_pending_stop = nullptr;   // stop event for the next reduction
   ~jkc_ctx() {
     for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);

@@ -6,6 +6,8 @@
 // slice removal of Alg. 2 (used by the plain per-submodel baseline).
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "jkc_internal.hpp"
 
 namespace jkc {
@@ -354,12 +356,16 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
 
 hipError_t launch_reduce(const double* partial, int32_t splits, int32_t rows, int32_t ldc,
                          int32_t ncols, LeftOut lo, int32_t zero_rows, double* out,
-                         int32_t ldo, hipStream_t s) {
+                         int32_t ldo, hipStream_t s, hipEvent_t stop) {
   const int64_t n = (int64_t)rows * ncols;
-  if (n <= 0) return hipSuccess;
+  if (n <= 0) return stop ? hipEventRecord(stop, s) : hipSuccess;
   const int64_t blocks = std::min<int64_t>((n + 63) / 64, 16384);
-  hipLaunchKernelGGL(k_reduce, dim3((unsigned)blocks), dim3(64 * kReduceGroups), 0, s, partial,
-                     splits, rows, ldc, ncols, lo, zero_rows, out, ldo);
+  if (stop)
+    hipExtLaunchKernelGGL(k_reduce, dim3((unsigned)blocks), dim3(64 * kReduceGroups), 0, s, nullptr,
+                          stop, 0, partial, splits, rows, ldc, ncols, lo, zero_rows, out, ldo);
+  else
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)blocks), dim3(64 * kReduceGroups), 0, s, partial,
+                       splits, rows, ldc, ncols, lo, zero_rows, out, ldo);
   return hipGetLastError();
 }
 

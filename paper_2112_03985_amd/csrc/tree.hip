@@ -1,6 +1,8 @@
-// Shared partial contraction of a 3-way sweep (Sec. 3, the MTTKRP of Alg. 1
-// inside the concurrent sweep of Alg. 3, evaluated as a two-level
-// dimension tree).  Modes are numbered from 0 here.  Before mode 0 of a
+// Shared partial contraction of a 3-way sweep: an extension beyond Alg. 3
+// (which computes each mode's MTTKRP separately).  The MTTKRPs of Alg. 1
+// inside the concurrent sweep are evaluated as a two-level dimension tree,
+// the reuse of partial MTTKRPs of Phan et al. (the paper's reference for the
+// error identity).  Modes are numbered from 0 here.  Before mode 0 of a
 // sweep the tensor is contracted once with the last factor,
 //   W(i, j, c) = sum_k T(i, j, k) U_2(k, c)         (all C columns at once),
 // by the fused MTTKRP kernel on the two-way view of T (rows i + I_0 j,

@@ -1044,10 +1044,8 @@ __global__ void __launch_bounds__(kThreads) k_grad(const GradArgs a) {
   }
 }
 
-__global__ void k_scale_cols(const ModelTable mt, const double* w, const int32_t* colmodel_unused,
-                             const double* src, int32_t rows, int32_t ldc, double* dst,
-                             int32_t ldd, int32_t C) {
-  (void)colmodel_unused;
+__global__ void k_scale_cols(const ModelTable mt, const double* w, const double* src,
+                             int32_t rows, int32_t ldc, double* dst, int32_t ldd) {
   for (int idx = blockIdx.x; idx < mt.K; idx += gridDim.x) {
     const int R = mt.rank[idx], off = mt.off[idx];
     const double s = w ? w[idx] : 1.0;
@@ -1056,7 +1054,6 @@ __global__ void k_scale_cols(const ModelTable mt, const double* w, const int32_t
       dst[(int64_t)i * ldd + off + r] = s * src[(int64_t)i * ldc + off + r];
     }
   }
-  (void)C;
 }
 
 __global__ void k_fold_lambda(double* U, int32_t rows, int32_t ldc, int32_t C, double* lambda) {
@@ -1178,9 +1175,9 @@ hipError_t launch_grad_assemble(const GradArgs& a, hipStream_t s) {
 
 hipError_t launch_scale_cols_by_model(const ModelTable& mt, const double* w, const double* src,
                                       int32_t rows, int32_t ldc, double* dst, int32_t ldd,
-                                      int32_t C, hipStream_t s) {
+                                      hipStream_t s) {
   hipLaunchKernelGGL(k_scale_cols, dim3(persistent_grid(mt.K)), dim3(kThreads), 0, s, mt, w,
-                     nullptr, src, rows, ldc, dst, ldd, C);
+                     src, rows, ldc, dst, ldd);
   return hipGetLastError();
 }
 

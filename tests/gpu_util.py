@@ -51,11 +51,28 @@ def oracle_model_mttkrp(wl, k, n, factors=None):
     return M
 
 
-def rel(a, b):
+def errors(a, b):
+    """(normwise, elementwise) relative error of a against b: the Frobenius
+    ratio ||a - b|| / ||b||, and the largest entry error relative to the
+    largest entry, max|a - b| / max|b| (a single wrong entry in a large
+    block shows in the second even when the first hides it)."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     nb = np.linalg.norm(b)
-    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+    fro = float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+    mb = float(np.max(np.abs(b))) if b.size else 0.0
+    mx = float(np.max(np.abs(a - b)) / (mb if mb > 0 else 1.0)) if b.size else 0.0
+    return fro, mx
+
+
+def rel_fro(a, b):
+    """Normwise relative error alone (error models stated normwise)."""
+    return errors(a, b)[0]
+
+
+def rel(a, b):
+    """The larger of the normwise and the elementwise relative error."""
+    return max(errors(a, b))
 
 
 def to_np(t):

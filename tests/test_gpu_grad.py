@@ -111,7 +111,7 @@ def test_refinement_matches_oracle():
         Ur = oracle.gd_refine(Tk, U, steps)
         Up = r.padded(Ur)
         for n in range(3):
-            assert rel(facs[n][:, cols(wl, k)], Up[n]) <= 1e-10, (k, n)
+            assert rel(facs[n][:, cols(wl, k)], Up[n]) <= 1e-11, (k, n)
 
 
 def test_config5_full_size_gradient_and_refinement():
@@ -142,7 +142,7 @@ def test_config5_full_size_gradient_and_refinement():
         Tk = oracle.reduce_tensor(T, 0, int(wl.left_out[k]))
         f, g = oracle.loss_and_grad(Tk, U)
         normT = np.sqrt(np.sum(Tk ** 2))
-        assert abs(L[k] - f) <= 1e-10 * max(1.0, 0.5 * normT ** 2), (k, L[k], f)
+        assert abs(L[k] - f) <= 1e-11 * max(1.0, 0.5 * normT ** 2), (k, L[k], f)
         gp = r.padded(g)
         for n in range(3):
             # the last updated mode's gradient is zero up to rounding, so the
@@ -152,4 +152,30 @@ def test_config5_full_size_gradient_and_refinement():
             assert err <= 1e-11 * max(scale, np.linalg.norm(gp[n])), (k, n, err, scale)
         Up = r.padded(oracle.gd_refine(Tk, U, steps))
         for n in range(3):
-            assert rel(facs[n][:, cols(wl, k)], Up[n]) <= 1e-10, (k, n)
+            assert rel(facs[n][:, cols(wl, k)], Up[n]) <= 1e-11, (k, n)
+
+
+def test_backward_after_a_second_forward_returns_its_own_gradient():
+    """Two forwards on one context before either backward: each graph node
+    keeps the gradients of its own point (they are copied out in forward),
+    so both backwards match the oracle at their own factors."""
+    import torch
+    wl = synth.random_problem(46, (11, 9, 8), [2, 3], [-1, 6], noise=0.2)
+    ctx = make_ctx(wl)
+    f1 = [torch.from_numpy(u).cuda().requires_grad_() for u in wl.init]
+    shifted = [u + 0.25 for u in wl.init]
+    f2 = [torch.from_numpy(u).cuda().requires_grad_() for u in shifted]
+    L1 = jk.JKCPLoss.apply(ctx, *f1)
+    L2 = jk.JKCPLoss.apply(ctx, *f2)
+    ctx.loss_grad()                      # a third evaluation overwrites the context's copy
+    g2 = [to_np(g) for g in torch.autograd.grad(L2.sum(), f2)]
+    g1 = [to_np(g) for g in torch.autograd.grad(L1.sum(), f1)]
+    for facs, got in ((wl.init, g1), (shifted, g2)):
+        for k in range(wl.K):
+            Tk, U, p = _reduced(wl, k, facs)
+            _, g = oracle.loss_and_grad(Tk, U)
+            for n in range(3):
+                gn = g[n]
+                if n == wl.sampled_mode and p >= 0:
+                    gn = np.insert(gn, p, 0.0, axis=0)
+                assert rel(got[n][:, cols(wl, k)], gn) <= 1e-11, (k, n)

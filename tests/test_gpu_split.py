@@ -2,20 +2,24 @@
 each operand split into two (three products, JKC_SPLIT_BF16X3) or three
 (six products, JKC_SPLIT_BF16X6) bfloat16 terms, float32 accumulation
 flushed to float64; everything after it in float64.  Errors are measured
-against the float64 oracle and printed.
+against the float64 oracle and printed for every result.
 
-Gate: 1e-5 relative per model.  The three-product form carries ~17 bits
-per operand, so its normwise error on sums that cancel can reach ~1e-5 by
-itself; it is therefore also checked against the error of the same
-representation evaluated exactly on the CPU (an error model, computed here
-from the inputs), and held to the gate on the split-precision workload."""
+Gate: 1e-5 relative per model and per iteration, applied where the normal
+matrices are well conditioned (kappa(H) <= 1e4).  The six-product split is
+held to it.  The three-product split keeps ~17 bits of every operand, so
+its normwise MTTKRP error on sums with random signs is itself about 1e-5
+(three error terms of up to 2^-16 each per product): it does not meet the
+gate on every input, and that is stated as a result.  Its MTTKRP is
+checked instead against the error of the same representation evaluated in
+exact (float64) arithmetic on the CPU -- the floor of any implementation
+of it."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
 import paper_2112_03985_amd as jk
-from gpu_util import make_ctx, oracle_model_mttkrp, rel, say, to_np, cols
+from gpu_util import make_ctx, oracle_model_mttkrp, errors, rel, rel_fro, say, to_np, cols
 
 pytestmark = pytest.mark.gpu
 
@@ -47,7 +51,7 @@ def _model_error_x3(wl, k, n):
     if n == wl.sampled_mode and p >= 0:
         M[p] = 0.0
         M3[p] = 0.0
-    return rel(M3, M)
+    return rel_fro(M3, M)
 
 
 SPECS = [
@@ -82,58 +86,127 @@ def test_bf16x3_mttkrp_matches_its_error_model(seed, dims, ranks, lo):
     for n in range(len(dims)):
         M = to_np(ctx.mttkrp(n))
         for k in range(wl.K):
-            e = rel(M[:, cols(wl, k)], oracle_model_mttkrp(wl, k, n))
+            e = rel_fro(M[:, cols(wl, k)], oracle_model_mttkrp(wl, k, n))
             floor = _model_error_x3(wl, k, n)
             worst = max(worst, e)
+            say("bf16x3 mttkrp mode %d model %d: %.3e (representation floor %.3e)" % (n, k, e, floor))
             assert e <= 1.25 * floor + 5e-7, (n, k, e, floor)
-            assert e <= 2e-5, (n, k, e)
     say("bf16x3 mttkrp worst rel err", worst)
 
 
 @pytest.mark.parametrize("prec", [jk.JKC_SPLIT_BF16X3, jk.JKC_SPLIT_BF16X6])
 def test_split_every_tiling(prec):
+    """Every compiled tiling, with K chunks: bf16x6 within the gate, bf16x3
+    within its representation floor."""
     wl = synth.random_problem(64, (67, 31, 26), [5, 9, 2], [-1, 66, 3], noise=0.01)
     ctx = make_ctx(wl, precision=prec)
     refs = {(n, k): oracle_model_mttkrp(wl, k, n) for n in range(3) for k in range(wl.K)}
+    floors = ({(n, k): _model_error_x3(wl, k, n) for n in range(3) for k in range(wl.K)}
+              if prec == jk.JKC_SPLIT_BF16X3 else None)
     for v in range(ctx.num_tilings()):
         for n in range(3):
             ctx.set_tiling(n, v, 4)
             M = to_np(ctx.mttkrp(n))
             for k in range(wl.K):
-                assert rel(M[:, cols(wl, k)], refs[(n, k)]) <= 2e-5, (v, n, k)
+                if floors is None:
+                    assert rel(M[:, cols(wl, k)], refs[(n, k)]) <= TOL, (v, n, k)
+                else:
+                    e = rel_fro(M[:, cols(wl, k)], refs[(n, k)])
+                    assert e <= 1.25 * floors[(n, k)] + 5e-7, (v, n, k, e)
 
 
-@pytest.mark.parametrize("prec", [jk.JKC_SPLIT_BF16X3, jk.JKC_SPLIT_BF16X6])
-def test_split_one_sweep_against_oracle(prec):
-    """One full sweep in split precision from the same init as the oracle:
-    factors and fit, errors printed.  Forward error of the update scales with
-    the conditioning of the normal matrices, so the gate is applied as
-    error / max(1, kappa(H) / 100).  Six products meet the 1e-5 gate; three
-    products carry ~17 bits per operand and are held to 5e-5 (observed
-    ~1.3e-5 here)."""
-    gate = TOL if prec == jk.JKC_SPLIT_BF16X6 else 5e-5
+def test_bf16x6_sweeps_against_oracle():
+    """Three sweeps in the six-product split from the same init as the
+    oracle: factors, lambda and error of every model after every sweep
+    within 1e-5 (the normal matrices here have kappa(H) <= 1e4, checked)."""
+    wl = synth.random_problem(65, (40, 30, 20), [4, 4, 4], [-1, 0, 39], noise=0.01, true_rank=4)
+    sweeps = 3
+    res = oracle.jk_als(np.asarray(wl.T), 0, wl.ranks, wl.left_out, wl.init, sweeps,
+                        record_factors=range(1, sweeps + 1))
+    ctx = make_ctx(wl, precision=jk.JKC_SPLIT_BF16X6)
+    worst = 0.0
+    for t in range(1, sweeps + 1):
+        ctx.sweep(1)
+        worst = max(worst, _compare_split_iteration(wl, ctx, res, t, TOL))
+    for k, r in res.items():
+        assert np.linalg.cond(r.H_last) <= 1e4
+    say("bf16x6 sweeps worst rel err", worst)
+
+
+def test_bf16x3_one_sweep_error_is_stated():
+    """One sweep in the three-product split: the error of every factor is
+    printed against the oracle and checked against the MTTKRP floor carried
+    through the solve (error <= 4 kappa(H) times the largest representation
+    floor of the model's MTTKRPs): a propagation model, not the 1e-5 gate,
+    which three products do not meet on this input."""
     wl = synth.random_problem(65, (40, 30, 20), [4, 4, 4], [-1, 0, 39], noise=0.01, true_rank=4)
     res = oracle.jk_als(np.asarray(wl.T), 0, wl.ranks, wl.left_out, wl.init, 1, record_factors=[1])
-    ctx = make_ctx(wl, precision=prec)
+    ctx = make_ctx(wl, precision=jk.JKC_SPLIT_BF16X3)
     ctx.sweep(1)
-    fit = to_np(ctx.get_status()[1])
-    worst = 0.0
     for k, r in res.items():
         kappa = float(np.linalg.cond(r.H_last))
+        floor = max(_model_error_x3(wl, k, n) for n in range(3))
         Up = r.padded(r.U_hist[1])
         for n in range(3):
-            e = rel(to_np(ctx.get_factors(n)[0])[:, cols(wl, k)], Up[n])
-            worst = max(worst, e)
-            assert e / max(1.0, kappa / 100.0) <= gate, (k, n, e, kappa)
-        assert abs(fit[k] - r.fit_hist[0]) <= gate
-    say("split one-sweep (precision %d) worst factor rel err" % prec, worst)
+            e = rel_fro(to_np(ctx.get_factors(n)[0])[:, cols(wl, k)], Up[n])
+            say("bf16x3 one sweep model %d mode %d: %.3e (kappa %.1f, MTTKRP floor %.3e)"
+                % (k, n, e, kappa, floor))
+            assert e <= 4.0 * kappa * floor, (k, n, e, kappa, floor)
+
+
+def _compare_split_iteration(wl, ctx, res, t, tol, models=None):
+    err = to_np(ctx.get_status()[0])
+    facs = [to_np(ctx.get_factors(n)[0]) for n in range(len(wl.dims))]
+    lam = to_np(ctx.get_factors(0)[1])
+    worst = 0.0
+    for k in (models if models is not None else res.keys()):
+        r = res[k]
+        c = cols(wl, k)
+        U_ref = r.padded(r.U_hist[t])
+        for n in range(len(wl.dims)):
+            fro, mx = errors(facs[n][:, c], U_ref[n])
+            say("sweep %d model %d mode %d: normwise %.3e, elementwise %.3e" % (t, k, n, fro, mx))
+            worst = max(worst, fro, mx)
+            assert max(fro, mx) <= tol, ("U", t, k, n, fro, mx)
+        e = rel(lam[c], r.lam_hist[t - 1])
+        ee = abs(err[k] - r.e_hist[t - 1]) / r.normT2
+        say("sweep %d model %d: lambda %.3e, error %.3e" % (t, k, e, ee))
+        assert e <= tol, ("lambda", t, k, e)
+        assert ee <= tol, ("err", t, k, ee)
+        worst = max(worst, e, ee)
+    return worst
+
+
+def test_config4_bf16x6_trajectory_sampled_models():
+    """The split-precision workload at full size (200x120x100x80, rank 12,
+    1 % noise, 200 leave-one-out models, C = 2400) in the six-product split:
+    4 sampled models compared with the oracle after each of 3 sweeps, every
+    result's error printed, gate 1e-5 (kappa(H) checked <= 1e4)."""
+    wl = _config4()
+    models = [0, 66, 133, 199]
+    sweeps = 3
+    say("c4 bf16x6 trajectory: oracle")
+    res = oracle.jk_als(np.asarray(wl.T), 0, wl.ranks, wl.left_out, wl.init, sweeps,
+                        models=models, record_factors=range(1, sweeps + 1))
+    say("c4 bf16x6 trajectory: GPU")
+    ctx = make_ctx(wl, precision=jk.JKC_SPLIT_BF16X6)
+    worst = 0.0
+    for t in range(1, sweeps + 1):
+        ctx.sweep(1)
+        worst = max(worst, _compare_split_iteration(wl, ctx, res, t, TOL, models=models))
+    for k in models:
+        assert np.linalg.cond(res[k].H_last) <= 1e4
+    say("c4 bf16x6 trajectory worst rel err", worst)
 
 
 @pytest.mark.parametrize("prec", [jk.JKC_SPLIT_BF16X3, jk.JKC_SPLIT_BF16X6])
 def test_config4_full_size_sampled_models(prec):
     """The split-precision workload at full size: 200x120x100x80 float64
     tensor of rank 12 with 1 % noise, 200 leave-one-out models of rank 12
-    (C = 2400); sampled models' MTTKRP in every mode, gate 1e-5."""
+    (C = 2400); sampled models' MTTKRP in every mode at the init, normwise
+    and elementwise errors printed, gate 1e-5 (met by both splits here: at
+    the init the sums do not cancel enough to reach the three-product
+    floor)."""
     wl = _config4()
     say("c4 full split mttkrp", prec)
     ctx = make_ctx(wl, precision=prec)
@@ -141,9 +214,10 @@ def test_config4_full_size_sampled_models(prec):
     for n in range(4):
         M = to_np(ctx.mttkrp(n))
         for k in (0, 199):
-            e = rel(M[:, cols(wl, k)], oracle_model_mttkrp(wl, k, n))
-            worst = max(worst, e)
-            assert e <= TOL, (n, k, e, ctx.describe(n))
+            fro, mx = errors(M[:, cols(wl, k)], oracle_model_mttkrp(wl, k, n))
+            say("c4 precision %d mode %d model %d: normwise %.3e, elementwise %.3e" % (prec, n, k, fro, mx))
+            worst = max(worst, fro, mx)
+            assert max(fro, mx) <= TOL, (n, k, fro, mx, ctx.describe(n))
     say("c4 worst rel err (precision %d)" % prec, worst)
 
 
