@@ -331,6 +331,39 @@ jkc_status jk_cals_profile_read(jkc_ctx *ctx, int64_t *launches, double *ms);
 jkc_status jk_cals_remove_slice(const jkc_problem *prob, const void *tensor,
                                 int32_t p, void *out);
 
+/* Bytes of the fixed device scratch jk_cals_mttkrp_static works in (one
+ * array per GPU the library runs on, held until the process ends). */
+#define JKC_STATIC_SCRATCH_BYTES (64ll << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the fused
+ * MTTKRP of jk_cals_mttkrp computed from caller buffers without a context or
+ * a workspace.  Its scratch -- the other modes' factors padded to the kernel's
+ * column pitch (left-out rows of the sampled mode zeroed), the column->model
+ * map and left-out row mask, and the split-K partials -- lives in a fixed
+ * library-owned device array of JKC_STATIC_SCRATCH_BYTES per GPU; nothing
+ * is allocated (no hipMalloc, no allocating library call).
+ *   prob    : as for jk_cals_init; precision must be JKC_FP64 (float64
+ *             matrix cores), tensor_dtype f64 or f32; copy_tensor and
+ *             tree_max_gib are ignored (T is read in place).
+ *   tensor  : device, layout above.
+ *   factors : host array [N] of device pointers; factors[m] (m != mode) is
+ *             I_m x C float64 row-major; factors[mode] is not read (may be
+ *             NULL).  The left-out rows of the sampled mode need not be zero.
+ *   out     : device I_mode x C float64 row-major; receives T_(mode) times
+ *             the multi-factor Khatri-Rao product, the left-out rows of each
+ *             model's columns set to 0 when mode is the sampled mode.
+ * The same tilings as jk_cals_mttkrp, with at most as many K splits as fit
+ * the scratch.  JKC_EINVAL when the padded factors and one output plane need
+ * more than JKC_STATIC_SCRATCH_BYTES (the message names both sizes),
+ * JKC_EUNSUPPORTED for split precisions.  Asynchronous on prob->stream
+ * except for two small table copies from pageable host memory, which finish
+ * before the call returns.  Every call on one GPU shares that GPU's scratch:
+ * calls that overlap on one GPU (other streams, other threads) race. */
+jkc_status jk_cals_mttkrp_static(const jkc_problem *prob, const void *tensor,
+                                 const double *const *factors, int32_t mode,
+                                 double *out);
+
 /* Free the host-side context (the workspace stays the caller's). */
 void jk_cals_destroy(jkc_ctx *ctx);
 

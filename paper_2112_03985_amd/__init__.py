@@ -101,6 +101,7 @@ def lib() -> ctypes.CDLL:
         "jk_cals_jackknife_std": (I32, [VP, I32, I32, I32, P(VP), VP, VP]),
         "jk_cals_set_compaction": (I32, [VP, I32]),
         "jk_cals_remove_slice": (I32, [P(Problem), VP, I32, VP]),
+        "jk_cals_mttkrp_static": (I32, [P(Problem), VP, P(VP), I32, VP]),
         "jk_cals_destroy": (None, [VP]),
         "jk_cals_last_error": (ctypes.c_char_p, []),
     }
@@ -516,6 +517,44 @@ def jk_cals_remove_slice(tensor, dims, sampled_mode, p, out=None, stream=None):
     prob, keep = make_problem(dims, sampled_mode, [1], [-1], tdt, JKC_FP64, 1, _stream(stream))
     _check(lib().jk_cals_remove_slice(ctypes.byref(prob), ctypes.c_void_p(tensor.data_ptr()),
                                       int(p), ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def jk_cals_mttkrp_static(tensor, dims, sampled_mode, ranks, left_out, factors, mode,
+                          out=None, stream=None):
+    """Fused MTTKRP of one mode from caller buffers, computed in the
+    library's fixed device scratch (no context, no workspace, nothing
+    allocated by the library; float64).  factors: N device float64
+    (I_m, C) tensors (factors[mode] may be None).  out: (I_mode, C) device
+    float64, allocated here when not given (pass it to allocate nothing)."""
+    import torch
+    dims = [int(x) for x in dims]
+    N = len(dims)
+    ranks = np.asarray(ranks, dtype=np.int32)
+    C = int(ranks.sum())
+    if not isinstance(tensor, torch.Tensor) or tensor.dtype not in (torch.float64, torch.float32):
+        raise TypeError("tensor must be a float64 or float32 torch tensor")
+    if not tensor.is_cuda or not tensor.is_contiguous():
+        raise ValueError("tensor must be a contiguous device tensor")
+    if tensor.numel() != int(np.prod(dims)):
+        raise ValueError("tensor has %d elements, dims say %d" % (tensor.numel(), int(np.prod(dims))))
+    if not 0 <= int(mode) < N:
+        raise ValueError("mode must be in 0..%d" % (N - 1))
+    mode = int(mode)
+    if len(factors) != N:
+        raise ValueError("factors must hold %d entries" % N)
+    for m in range(N):
+        if m != mode:
+            _check_buffer(factors[m], (dims[m], C), "factors[%d]" % m, device=tensor.device)
+    if out is None:
+        out = torch.empty((dims[mode], C), dtype=torch.float64, device=tensor.device)
+    _check_buffer(out, (dims[mode], C), "out", device=tensor.device)
+    tdt = JKC_TENSOR_F64 if tensor.dtype == torch.float64 else JKC_TENSOR_F32
+    prob, keep = make_problem(dims, sampled_mode, ranks, left_out, tdt, JKC_FP64, 1, _stream(stream))
+    ptrs = (ctypes.c_void_p * N)(*[0 if (m == mode or factors[m] is None) else factors[m].data_ptr()
+                                    for m in range(N)])
+    _check(lib().jk_cals_mttkrp_static(ctypes.byref(prob), ctypes.c_void_p(tensor.data_ptr()),
+                                       ptrs, mode, ctypes.c_void_p(out.data_ptr())))
     return out
 
 

@@ -803,6 +803,39 @@ jkc_status enqueue_loss_grad(jkc_ctx* ctx, double* loss) {
   return JKC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Fixed device scratch of jk_cals_mttkrp_static, for callers that cannot
+// allocate.  In host code the array's name is only a host-side stand-in:
+// its device address comes from hipGetSymbolAddress, taken once per device
+// with that device current, and only that address is handed to kernels and
+// copies.
+// ---------------------------------------------------------------------------
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char g_static_scratch[JKC_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+// Device address of the fixed scratch on the current device.
+jkc_status static_scratch_address(void** out) {
+  int dev = -1;
+  JKC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(JKC_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    JKC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(g_static_scratch)));
+    if (!p) return fail(JKC_EDEVICE, "hipGetSymbolAddress returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return JKC_OK;
+}
+
 jkc_status check_ctx(const jkc_ctx* ctx) {
   if (!ctx) return fail(JKC_EINVAL, "context is NULL");
   return JKC_OK;
@@ -1033,6 +1066,107 @@ jkc_status jk_cals_mttkrp(jkc_ctx* ctx, int32_t mode, double* out) {
   JKC_TRY(launch_reduce_timed(ctx, splits > 1 ? ctx->partial : ctx->Mbuf, splits,
                               (int32_t)ctx->dims[mode], ctx->C, mode == ctx->nhat ? 1 : 0, out,
                               ctx->C));
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_mttkrp_static(const jkc_problem* prob, const void* tensor,
+                                 const double* const* factors, int32_t mode, double* out) {
+  Plan pl;
+  JKC_TRY(make_plan(prob, &pl));
+  if (pl.precision != JKC_FP64)
+    return fail(JKC_EUNSUPPORTED, "jk_cals_mttkrp_static computes in float64 only (precision 0)");
+  if (!tensor) return fail(JKC_EINVAL, "tensor is NULL");
+  if (!factors) return fail(JKC_EINVAL, "factors is NULL");
+  if (mode < 0 || mode >= pl.N) return fail(JKC_EINVAL, "mode out of range");
+  for (int m = 0; m < pl.N; ++m)
+    if (m != mode && !factors[m])
+      return fail(JKC_EINVAL, "factors[" + std::to_string(m) + "] is NULL");
+  if (!out) return fail(JKC_EINVAL, "out is NULL");
+
+  // Scratch layout: column -> model map, left-out row mask, the other
+  // modes' factors padded to ldc columns (left-out rows zeroed), then the
+  // split-K partials (at least one plane: the unsplit product).
+  const int64_t Ih = pl.dims[pl.nhat];
+  int64_t pos = 0;
+  const int64_t off_colmodel = pos;
+  pos += align_up((int64_t)pl.ldc * 4, kAlign);
+  const int64_t off_lomask = pos;
+  pos += align_up(Ih * pl.K, kAlign);
+  int64_t off_u[kMaxOrder] = {0, 0, 0, 0};
+  for (int m = 0; m < pl.N; ++m) {
+    if (m == mode) continue;
+    off_u[m] = pos;
+    pos += align_up(pl.dims[m] * pl.ldc * 8, kAlign);
+  }
+  const int64_t plane = pl.dims[mode] * pl.ldc * 8;
+  const int64_t off_part = pos;
+  if (pos + plane > (int64_t)JKC_STATIC_SCRATCH_BYTES)
+    return fail(JKC_EINVAL, "problem needs " + std::to_string(pos + plane) +
+                                " bytes of scratch; the fixed scratch holds " +
+                                std::to_string((int64_t)JKC_STATIC_SCRATCH_BYTES));
+  const int split_room = (int)std::min<int64_t>(((int64_t)JKC_STATIC_SCRATCH_BYTES - pos) / plane,
+                                                1 << 20);
+
+  // A host-side context over the scratch: the launch path of jk_cals_mttkrp.
+  jkc_ctx c;
+  c.N = pl.N;
+  c.nhat = pl.nhat;
+  c.K = pl.K;
+  c.C = pl.C;
+  c.C_act = pl.C;
+  c.ldc = pl.ldc;
+  c.P = pl.P;
+  for (int n = 0; n < kMaxOrder; ++n) {
+    c.dims[n] = pl.dims[n];
+    c.strides[n] = pl.strides[n];
+  }
+  c.tensor_f32 = pl.tensor_f32;
+  c.precision = pl.precision;
+  c.stream = static_cast<hipStream_t>(prob->stream);
+  c.T = tensor;
+  c.split_max[mode] = std::max(1, std::min(pl.split_max[mode], split_room));
+  const auto& vars = variants_for(&c);
+  const ModeShape shape = mode_shape(&c, mode, c.split_max[mode]);
+  Tiling t;
+  if (!tune_lookup(&c, mode, vars, shape, &t)) t = choose_tiling(vars, shape);
+  if (t.variant < 0) return fail(JKC_EUNSUPPORTED, "no MTTKRP tiling for this shape");
+  const int splits = effective_splits(&c, mode, t);
+  c.partial_doubles = (int64_t)split_room * pl.dims[mode] * pl.ldc;
+  if (splits > split_room) return fail(JKC_ESTATE, "split-K partials exceed the fixed scratch");
+
+  std::vector<int32_t> colmodel(pl.ldc, -1);
+  std::vector<uint8_t> lomask(Ih * pl.K, 0);
+  for (int k = 0, off = 0; k < pl.K; ++k) {
+    for (int r = 0; r < prob->ranks[k]; ++r) colmodel[off + r] = k;
+    off += prob->ranks[k];
+    const int32_t* rows = prob->left_out + (int64_t)k * pl.del_d;
+    for (int j = 0; j < pl.del_d; ++j)
+      if (rows[j] >= 0) lomask[(int64_t)rows[j] * pl.K + k] = 1;
+  }
+
+  // every check done: device work from here on
+  void* sp = nullptr;
+  JKC_TRY(static_scratch_address(&sp));
+  char* base = static_cast<char*>(sp);
+  c.d_colmodel = reinterpret_cast<int32_t*>(base + off_colmodel);
+  c.d_lomask = reinterpret_cast<uint8_t*>(base + off_lomask);
+  for (int m = 0; m < pl.N; ++m)
+    if (m != mode) c.U[m] = reinterpret_cast<double*>(base + off_u[m]);
+  c.partial = reinterpret_cast<double*>(base + off_part);
+  c.Mbuf = c.partial;
+  hipStream_t st = c.stream;
+  // pageable host sources: these copies complete before the calls return
+  JKC_HIP(hipMemcpyAsync(c.d_colmodel, colmodel.data(), colmodel.size() * 4,
+                         hipMemcpyHostToDevice, st));
+  JKC_HIP(hipMemcpyAsync(c.d_lomask, lomask.data(), lomask.size(), hipMemcpyHostToDevice, st));
+  for (int m = 0; m < pl.N; ++m)
+    if (m != mode)
+      JKC_HIP(launch_pack_factor(factors[m], pl.C, (int32_t)pl.dims[m], pl.C, pl.ldc, c.left_out(),
+                                 m == pl.nhat ? 1 : 0, c.U[m], st));
+  JKC_TRY(enqueue_mttkrp(&c, mode, t, true));
+  JKC_TRY(launch_reduce_timed(&c, c.partial, splits, (int32_t)pl.dims[mode], pl.C,
+                              mode == pl.nhat ? 1 : 0, out, pl.C));
   g_last_error.clear();
   return JKC_OK;
 }

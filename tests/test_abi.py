@@ -166,3 +166,25 @@ def test_remove_slice_validation(L):
     assert L.jk_cals_remove_slice(None, t, 0, o) == jk.JKC_EINVAL
     prob1, keep1 = jk.make_problem([4, 1, 6], 1, [1], [-1])
     assert L.jk_cals_remove_slice(ctypes.byref(prob1), t, 0, o) == jk.JKC_EINVAL
+
+
+def test_static_mttkrp_validates_before_any_device_work(L):
+    """jk_cals_mttkrp_static checks everything on the host first: a problem
+    whose padded factors and output plane exceed the fixed scratch, a split
+    precision, a NULL factor and a bad mode are refused (no pointer here is
+    a real device address; none is touched)."""
+    fake = ctypes.c_void_p(1 << 20)
+    ptrs = (ctypes.c_void_p * 3)(1 << 20, 1 << 20, 1 << 20)
+    # 5000 x 4000 x 2, C = 1024: one mode-0 output plane is 41 MB and the
+    # padded mode-1 factor 33 MB, together above the 64 MiB scratch
+    prob, keep = jk.make_problem([5000, 4000, 2], 0, [32] * 32, [-1] * 32)
+    assert L.jk_cals_mttkrp_static(ctypes.byref(prob), fake, ptrs, 0, fake) == jk.JKC_EINVAL
+    assert "scratch" in jk.jk_cals_last_error()
+    prob, keep = jk.make_problem([4, 5, 6], 0, [2, 3], [-1, 3], precision=jk.JKC_SPLIT_BF16X3)
+    assert L.jk_cals_mttkrp_static(ctypes.byref(prob), fake, ptrs, 0, fake) == jk.JKC_EUNSUPPORTED
+    prob, keep = jk.make_problem([4, 5, 6], 0, [2, 3], [-1, 3])
+    assert L.jk_cals_mttkrp_static(ctypes.byref(prob), fake, ptrs, 3, fake) == jk.JKC_EINVAL
+    nulls = (ctypes.c_void_p * 3)(1 << 20, None, 1 << 20)
+    assert L.jk_cals_mttkrp_static(ctypes.byref(prob), fake, nulls, 0, fake) == jk.JKC_EINVAL
+    assert "factors[1]" in jk.jk_cals_last_error()
+    assert L.jk_cals_mttkrp_static(ctypes.byref(prob), fake, ptrs, 0, None) == jk.JKC_EINVAL
