@@ -54,6 +54,26 @@ constexpr size_t kMaxTimedLaunches = 65536;
 
 int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+// K step of the split-precision kernels (one v_mfma_f32_16x16x32_bf16 deep).
+constexpr int64_t kSplitStep = 32;
+
+// Low mode of the split-precision unfolding of mode n (see Plan::split_low).
+int split_low_mode(int N, const int64_t* dims, int n) {
+  int best = -1;
+  for (int m = 0; m < N; ++m) {
+    if (m == n) continue;
+    if (best < 0) {
+      best = m;
+      continue;
+    }
+    // waste: padded / actual, compared exactly by cross-multiplication
+    const int64_t pm = align_up(dims[m], kSplitStep), pb = align_up(dims[best], kSplitStep);
+    const int64_t lhs = pm * dims[best], rhs = pb * dims[m];
+    if (lhs < rhs || (lhs == rhs && dims[m] > dims[best])) best = m;
+  }
+  return best;
+}
+
 // Sizes derived from a validated problem, shared by the size query and init.
 struct Plan {
   int N = 0, nhat = 0, K = 0, C = 0, ldc = 0;
@@ -73,8 +93,14 @@ struct Plan {
   std::vector<Item> items;
   int64_t total = 0;
 
-  // row pitch of the split-precision unfolded copy of mode n
-  int64_t split_ld(int n) const { return align_up(P / dims[n], 8); }
+  // Split-precision layout of mode n: the unfolding's columns ordered low
+  // mode first (the other mode whose size pads to a multiple of the 32-K
+  // step with the least waste, the larger size on ties), index padded to
+  // split_ilp(n), then the remaining modes ("wraps").
+  int split_low(int n) const { return split_low_mode(N, dims, n); }
+  int64_t split_ilp(int n) const { return align_up(dims[split_low(n)], kSplitStep); }
+  int64_t split_wraps(int n) const { return P / (dims[n] * dims[split_low(n)]); }
+  int64_t split_ld(int n) const { return split_ilp(n) * split_wraps(n); }
 
   void layout() {
     items.clear();
@@ -111,8 +137,14 @@ struct Plan {
     items.push_back({"slice_part", (int64_t)kSliceChunks * dims[nhat] * 8});
     items.push_back({"counter", 4});
     items.push_back({"upart", update_rows_scratch(maxI, gsize, K) * 8});
-    // split paths: float32 copies of the factors, refreshed before each MTTKRP
-    for (int n = 0; n < N; ++n) items.push_back({"Uf", precision != JKC_FP64 ? dims[n] * ldc * 4 : 0});
+    // split paths: the low mode's factor in bfloat16 terms, transposed and
+    // padded ([term][ldc][ilp]), refreshed before each MTTKRP
+    int64_t usplit = 0;
+    if (precision != JKC_FP64) {
+      const int nterm = precision == JKC_SPLIT_BF16X6 ? 3 : 2;
+      for (int n = 0; n < N; ++n) usplit = std::max(usplit, (int64_t)nterm * ldc * split_ilp(n) * 2);
+    }
+    items.push_back({"Usplit", usplit});
     // jackknife post-processing: matched components and signed inverse norms
     items.push_back({"jk_perm", (int64_t)ldc * 4});
     items.push_back({"jk_scale", (int64_t)N * ldc * 8});
@@ -207,14 +239,16 @@ jkc_status make_plan(const jkc_problem* prob, Plan* pl) {
     return fail(JKC_EINVAL, "copy_tensor = 0 needs precision JKC_FP64");
   if (pl->precision != JKC_FP64)
     for (int n = 0; n < pl->N; ++n)
-      if (pl->dims[n] * align_up(P / pl->dims[n], 8) >= (1ll << 31) ||
-          pl->dims[n] * (int64_t)pl->ldc >= (1ll << 31))
+      if (pl->dims[n] * pl->split_ld(n) >= (1ll << 31) ||
+          pl->dims[n] * (int64_t)pl->ldc >= (1ll << 31) ||
+          pl->split_ilp(n) * (int64_t)pl->ldc >= (1ll << 31))
         return fail(JKC_EINVAL, "split precision needs every unfolding and factor below 2^31 elements");
   pl->maxI = 0;
   pl->partial_doubles = 0;
   for (int n = 0; n < pl->N; ++n) {
     pl->maxI = std::max(pl->maxI, pl->dims[n]);
-    const int64_t J = P / pl->dims[n];
+    // split paths cut K at whole wraps
+    const int64_t J = pl->precision != JKC_FP64 ? pl->split_wraps(n) * 64 : P / pl->dims[n];
     pl->split_max[n] = split_cap(pl->dims[n], pl->ldc, J);
     if (pl->split_max[n] > 1)
       pl->partial_doubles =
@@ -311,7 +345,8 @@ Tiling choose_tiling(const std::vector<MttkrpVariant>& vars, const ModeShape& s)
 ModeShape mode_shape(const jkc_ctx* ctx, int n, int split_max) {
   ModeShape s;
   s.M = ctx->dims[n];
-  s.J = ctx->P / ctx->dims[n];
+  s.J = ctx->nterm > 0 ? (int64_t)ctx->tp_ilp[n] * (ctx->P / (ctx->dims[n] * ctx->dims[ctx->tp_low[n]]))
+                       : ctx->P / ctx->dims[n];
   s.ncols = ctx->C;
   s.ldc = ctx->ldc;
   s.split_max = split_max;
@@ -445,23 +480,30 @@ jkc_status launch_mttkrp_timed(jkc_ctx* ctx, const MttkrpArgs& a, const Tiling& 
 // ctx->partial (t.splits > 1) or the product itself in ctx->Mbuf.  When
 // reduce_follows, the reduction launched next (launch_reduce_timed) closes
 // the launch's timing window.
+// K chunking of mode n's MTTKRP under tiling t: K elements per split and
+// the number of splits (split paths: whole wraps of the low mode).
+void chunking(const jkc_ctx* ctx, int n, const Tiling& t, int64_t* kchunk, int* splits) {
+  int64_t J, step;
+  if (ctx->nterm > 0) {
+    J = ctx->P / (ctx->dims[n] * ctx->dims[ctx->tp_low[n]]);   // wraps
+    step = 1;
+  } else {
+    J = ctx->P / ctx->dims[n];
+    step = t.bk;
+  }
+  int64_t kc = align_up((J + t.splits - 1) / t.splits, step);
+  *kchunk = kc;
+  *splits = (int)((J + kc - 1) / kc);
+}
+
+// Enqueue the fused MTTKRP of mode n.  Result: split-K partials in
+// ctx->partial (t.splits > 1) or the product itself in ctx->Mbuf.  When
+// reduce_follows, the reduction launched next (launch_reduce_timed) closes
+// the launch's timing window.
 jkc_status enqueue_mttkrp(jkc_ctx* ctx, int n, const Tiling& t, bool reduce_follows = false) {
   const auto& vars = variants_for(ctx);
   if (t.variant < 0 || t.variant >= (int)vars.size()) return fail(JKC_ESTATE, "no tiling");
   MttkrpArgs a{};
-  if (ctx->nterm > 0) {
-    a.T = ctx->T_planes + ctx->tp_off[n];
-    a.plane = ctx->dims[n] * ctx->tp_ld[n];
-    a.ldt = ctx->tp_ld[n];
-    for (int m = 0, q = 0; m < ctx->N; ++m) {
-      if (m == n) continue;
-      JKC_HIP(launch_to_f32(ctx->U[m], ctx->dims[m] * ctx->ldc, ctx->Uf[m], ctx->stream));
-      a.oUf[q++] = ctx->Uf[m];
-    }
-  } else {
-    a.T = ctx->T;
-    a.plane = 0;
-  }
   a.t_is_f32 = ctx->tensor_f32;
   int q = 0;
   for (int m = 0; m < ctx->N; ++m) {
@@ -480,13 +522,42 @@ jkc_status enqueue_mttkrp(jkc_ctx* ctx, int n, const Tiling& t, bool reduce_foll
   a.stride_n = ctx->strides[n];
   a.M = (int32_t)ctx->dims[n];
   a.J = ctx->P / ctx->dims[n];
+  if (ctx->nterm > 0) {
+    // the low mode's factor split into bfloat16 terms, transposed and padded
+    const int low = ctx->tp_low[n];
+    a.il = (int32_t)ctx->dims[low];
+    a.ilp = ctx->tp_ilp[n];
+    a.wraps = ctx->P / (ctx->dims[n] * ctx->dims[low]);
+    a.ldt = (int64_t)a.ilp * a.wraps;
+    a.J = a.ldt;
+    a.T = ctx->T_planes + ctx->tp_off[n];
+    a.plane = ctx->dims[n] * a.ldt;
+    a.ut = ctx->Usplit;
+    a.ut_plane = (int64_t)ctx->ldc * a.ilp;
+    JKC_HIP(launch_split_factor_t(ctx->U[low], a.il, ctx->ldc, a.ilp, ctx->nterm, ctx->Usplit,
+                                  ctx->stream));
+    a.nh = 0;
+    for (int m = 0; m < ctx->N; ++m) {
+      if (m == n || m == low) continue;
+      a.hU[a.nh] = ctx->U[m];
+      a.hdim[a.nh] = (int32_t)ctx->dims[m];
+      ++a.nh;
+    }
+    for (int h = a.nh; h < kMaxOrder - 2; ++h) {
+      a.hU[h] = nullptr;
+      a.hdim[h] = 1;
+    }
+  } else {
+    a.T = ctx->T;
+    a.plane = 0;
+  }
   a.ldc = ctx->ldc;
   a.ncols = ctx->C_act;
   a.mtiles = (int32_t)((a.M + t.bm() - 1) / t.bm());
   a.ntiles = (int32_t)((a.ncols + t.bn() - 1) / t.bn());
-  int64_t kchunk = (a.J + t.splits - 1) / t.splits;
-  kchunk = align_up(kchunk, t.bk);
-  const int splits = (int)((a.J + kchunk - 1) / kchunk);
+  int64_t kchunk = 0;
+  int splits = 1;
+  chunking(ctx, n, t, &kchunk, &splits);
   a.kchunk = kchunk;
   a.splits = splits;
   if (splits > 1) {
@@ -548,9 +619,10 @@ jkc_status launch_reduce_timed(jkc_ctx* ctx, const double* partial, int32_t spli
 }
 
 int effective_splits(const jkc_ctx* ctx, int n, const Tiling& t) {
-  const int64_t J = ctx->P / ctx->dims[n];
-  int64_t kchunk = align_up((J + t.splits - 1) / t.splits, t.bk);
-  return (int)((J + kchunk - 1) / kchunk);
+  int64_t kchunk = 0;
+  int splits = 1;
+  chunking(ctx, n, t, &kchunk, &splits);
+  return splits;
 }
 
 // MTTKRP of mode n reduced into out (ld ldo, ncols columns), with the Case I
@@ -964,7 +1036,7 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
   c.slice_part = static_cast<double*>(take(it++));
   c.counter = static_cast<int32_t*>(take(it++));
   c.upart = static_cast<double*>(take(it++));
-  for (int n = 0; n < pl.N; ++n) c.Uf[n] = static_cast<float*>(take(it++));
+  c.Usplit = static_cast<uint16_t*>(take(it++));
   c.jk_perm = static_cast<int32_t*>(take(it++));
   c.jk_scale = static_cast<double*>(take(it++));
   c.d_colmap = static_cast<int32_t*>(take(it++));
@@ -989,8 +1061,10 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
     for (int n = 0; n < pl.N; ++n) {
       c.tp_off[n] = off;
       c.tp_ld[n] = pl.split_ld(n);
-      JKC_HIP(launch_split_unfold(tensor, pl.tensor_f32, pl.N, pl.dims, n, c.tp_ld[n], c.nterm,
-                                  c.T_planes + off, st));
+      c.tp_low[n] = pl.split_low(n);
+      c.tp_ilp[n] = (int32_t)pl.split_ilp(n);
+      JKC_HIP(launch_split_unfold(tensor, pl.tensor_f32, pl.N, pl.dims, n, c.tp_low[n], c.tp_ilp[n],
+                                  c.nterm, c.T_planes + off, st));
       off += (int64_t)c.nterm * pl.dims[n] * c.tp_ld[n];
     }
   } else if (pl.copy_tensor) {

@@ -48,9 +48,18 @@ struct MttkrpArgs {
   int64_t stride_n;         // tensor stride of the output mode
   int32_t M;                // I_n (output rows)
   int64_t J;                // columns of the unfolding
-  int64_t kchunk;           // K elements per split (multiple of BK)
-  int64_t ldt;              // split paths: row pitch of the unfolded planes
-  const float* oUf[kMaxOrder - 1];   // split paths: float32 copies of oU
+  int64_t kchunk;           // K elements per split (multiple of BK); split paths: wraps
+  // Split paths.  The unfolding's columns are ordered (low, higher modes
+  // ascending) with the low mode's index padded to ilp (a multiple of the
+  // kernel's K step): column jl + ilp * w for wrap w of the higher modes.
+  int64_t ldt;              // row pitch of the unfolded planes (ilp * wraps)
+  const uint16_t* ut;       // low mode's factor in bfloat16 terms, [term][ilp/32][ldc][32]
+  int64_t ut_plane;         // elements between the terms of ut
+  int32_t il, ilp;          // low mode size and its padded size
+  int32_t nh;               // number of higher modes (N - 2)
+  const double* hU[kMaxOrder - 2];   // higher modes' float64 factors, ascending
+  int32_t hdim[kMaxOrder - 2];       // their sizes
+  int64_t wraps;            // product of the higher modes' sizes
   int32_t ldc;              // leading dimension of factors and partials
   int32_t ncols;            // columns to produce (<= ldc)
   int32_t mtiles, ntiles;
@@ -173,13 +182,19 @@ hipError_t launch_reduce(const double* partial, int32_t splits, int32_t rows,
 // Preparation kernels.
 hipError_t launch_copy_tensor(const void* src, int32_t src_f32, void* dst,
                               int64_t count, hipStream_t s);
-// Split-precision tensor copy of one mode: the mode-n unfolding (Eq. (3))
-// stored row-major with row pitch ldt (>= P / I_n, a multiple of 8, padding
-// zero), as nterm bfloat16 planes of I_n * ldt elements.
-hipError_t launch_to_f32(const double* src, int64_t n, float* dst, hipStream_t s);
+// Split-precision tensor copy of one mode: the mode-n unfolding with its
+// columns ordered low mode first (index padded to ilp with zeros), then the
+// other modes ascending (lowest fastest), in K blocks of 32 (element (i, k)
+// at ((k / 32) * I_n + i) * 32 + k % 32), as nterm bfloat16 planes of
+// I_n * ilp * wraps elements.
 hipError_t launch_split_unfold(const void* src, int32_t src_f32, int32_t N, const int64_t* dims,
-                               int32_t n, int64_t ldt, int32_t nterm, uint16_t* planes,
-                               hipStream_t s);
+                               int32_t n, int32_t low, int32_t ilp, int32_t nterm,
+                               uint16_t* planes, hipStream_t s);
+// The low mode's factor (rows x ldc float64) as nterm bfloat16 terms in K
+// blocks of 32 rows: term t of U(j, c) at out + t * ldc * ilp +
+// ((j / 32) * ldc + c) * 32 + j % 32 (0 for rows <= j < ilp).
+hipError_t launch_split_factor_t(const double* U, int32_t rows, int32_t ldc, int32_t ilp,
+                                 int32_t nterm, uint16_t* out, hipStream_t s);
 hipError_t launch_slice_norms(const void* T, int32_t t_f32, int64_t inner,
                               int32_t I, int64_t outer, double* partial,
                               int32_t chunks, double* s_out, hipStream_t s);
@@ -252,7 +267,9 @@ struct jkc_ctx {
   int64_t tp_off[jkc::kMaxOrder] = {0, 0, 0, 0};   // element offset of mode n's planes
   int64_t tp_ld[jkc::kMaxOrder] = {0, 0, 0, 0};    // their row pitch
   double* U[jkc::kMaxOrder] = {nullptr, nullptr, nullptr, nullptr};
-  float* Uf[jkc::kMaxOrder] = {nullptr, nullptr, nullptr, nullptr};   // split paths
+  uint16_t* Usplit = nullptr;    // split paths: the low mode's factor in bf16 terms
+  int32_t tp_low[jkc::kMaxOrder] = {0, 0, 0, 0};   // split paths: low mode of each mode
+  int32_t tp_ilp[jkc::kMaxOrder] = {0, 0, 0, 0};   // and its padded size
   double* G[jkc::kMaxOrder] = {nullptr, nullptr, nullptr, nullptr};
   double* Mbuf = nullptr;        // [max I_n][ldc]
   double* partial = nullptr;     // split-K partials

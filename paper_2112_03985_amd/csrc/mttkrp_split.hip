@@ -1,50 +1,48 @@
 // Split-precision fused MTTKRP: the same product as the float64 kernel
-// (Alg. 3, MTTKRP step, over the full tensor with on-the-fly Khatri-Rao
-// tiles), computed on the bfloat16 matrix cores.
+// (Alg. 3, MTTKRP step, over the full tensor, column-concatenated over all
+// models; Eq. (1) per model), computed on the bfloat16 matrix cores.
 //
-// Every operand x is written as a sum of NTERM bfloat16 terms, each the
-// round-to-nearest-even of what the previous terms leave (x1 = bf16(x),
-// x2 = bf16(x - x1), ...): the tensor once at init, directly from float64;
-// the Khatri-Rao entries as they are generated, from a float32 product of the
-// factor entries (read from float32 copies of the factors made before each
-// launch).  Products keep every term pair whose magnitude is at least
-// 2^-8(NTERM-1) of the leading one:
+// Factorisation of the Khatri-Rao product.  Pick one other mode L (the
+// "low" mode) and write the remaining other modes' multi-index as a wrap w.
+// Then
+//   M_n(i, c) = sum_w s(w, c) * sum_jl T_(n)(i, jl, w) * U_L(jl, c),
+//   s(w, c)   = prod_{m != n, L} U_m(w_m, c),
+// so within one wrap the product is a plain GEMM of a tensor slab with U_L
+// (the same B operand for every wrap), and the remaining Khatri-Rao factor
+// is one float64 scale per (wrap, column), applied when the wrap's float32
+// accumulators are added into the float64 ones.  Nothing is formed per
+// Khatri-Rao entry in the inner loop: both operands are copied to LDS as
+// loaded.  (The same multilinear identity as Eq. (1); only the evaluation
+// order of the sums differs.)
+//
+// Operands as sums of NTERM bfloat16 terms, each the round-to-nearest-even
+// of what the previous terms leave (x1 = bf16(x), x2 = bf16(x - x1), ...):
+// the tensor once at init, U_L before each launch, both from float64.
+// Products keep every term pair whose magnitude is at least 2^-8(NTERM-1)
+// of the leading one:
 //   NTERM = 2: a1 b1 + a1 b2 + a2 b1                       (3 MFMA products)
 //   NTERM = 3: the above + a1 b3 + a2 b2 + a3 b1           (6 MFMA products)
 // smallest terms first.  Products of bfloat16 are exact in float32; the
-// float32 accumulators are added into float64 ones after at most 2048
-// columns of K, and split-K partials are float64.
+// float32 accumulators hold one wrap (at most 2048 K) before they are scaled
+// and added into float64 ones; split-K partials are float64.
 //
-// Accuracy: with two terms each operand carries ~17 bits and the result's
-// normwise relative error is ~2^-17 times the ratio sum|T||KRP| / |M| (the
-// cancellation in the MTTKRP sums), i.e. a few 1e-6 on data without
-// cancellation and about 1e-5 when the sums cancel by half; with three
-// terms it is ~2^-23 times that ratio.
+// Layout (written by the prep kernels).  For the split paths the tensor is
+// held once per mode as that mode's unfolding with its columns ordered
+// jl + ilp * w (jl padded with zeros to ilp, a multiple of the 32-K step),
+// one plane per term, in K blocks of 32: the 32-K slice of all rows is one
+// contiguous run, so a step's A operand (BM rows x 32 K) spans one or two
+// pages whatever the tensor size (a row-major unfolding puts every row of
+// the tile megabytes apart).  U_L is held the same way ([term][K block][c]
+// [32], padded with zero rows).  Both operands arrive as aligned 16-byte
+// runs of 8 consecutive K, the register layout of the
+// v_mfma_f32_16x16x32_bf16 operands, and are copied to LDS unchanged.
 //
-// Layout.  For the split paths the tensor is held once per mode as that
-// mode's unfolding (Eq. (3)) stored row-major, rows padded to a multiple of
-// 8 columns, one plane per term.  A row of the unfolding is then contiguous,
-// so the A operand of a step (BM rows x 32 columns) arrives as aligned
-// 16-byte loads of 8 consecutive K for one row -- exactly the register
-// layout of the v_mfma_f32_16x16x32_bf16 operands -- and is copied to LDS
-// unchanged.
-//
-// Khatri-Rao generation.  A thread owns one column c of the tile and a run
-// of 8 consecutive K (columns j of the unfolding).  Within the run the
-// lowest other mode's index advances and the higher modes' indices stay
-// fixed unless the run wraps; the product of the higher modes' entries is
-// formed once per run and multiplied by the 8 entries of the lowest mode
-// (the order highest mode first, as in Eq. (1)).  Runs that wrap take a
-// per-entry path.  Each entry is split into its bfloat16 terms with the
-// hardware round-to-nearest-even conversion and 8 terms are written to LDS
-// as one 16-byte store, again in the operand's register layout.
-//
-// Tiles are BM x BN with BM = 16 WM TM covering all rows of small modes, so
-// each Khatri-Rao entry is generated once per column tile; blocks are dealt
-// to the XCDs in contiguous runs of column tiles (they share the tensor
-// slice in L2).  The loads of a step are issued two steps before it is
-// stored (two register stages), the store runs after the matrix-core work of
-// the step before it (double-buffered LDS, one barrier per step).
+// Tiles are BM x BN, BM = 16 WM TM; a block walks whole wraps of one K
+// chunk; blocks are dealt to the XCDs in contiguous runs of column tiles
+// (they share the tensor slab in L2).  Loads of a step are issued two steps
+// before it is stored (two register stages); the store of step s+1 runs
+// interleaved with the matrix instructions of step s (double-buffered LDS,
+// one barrier per step).
 #include <type_traits>
 
 #include <hip/hip_ext.h>
@@ -61,54 +59,40 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int kBK = 32;           // one v_mfma_f32_16x16x32_bf16 deep
-constexpr int kLdk = kBK + 8;     // LDS row pitch in bf16 elements (80 bytes)
-constexpr int kFlushK = 2048;     // float32 accumulation span before a float64 flush
+constexpr int kFlushSteps = 64;   // float32 accumulation span within a long wrap (2048 K)
 constexpr int kXcds = 8;
 
-// Multi-index of the other modes for column j of the unfolding (lowest
-// other mode fastest, Eq. (3)), advanced incrementally.
-struct Walk {
-  uint32_t idx[kMaxOrder - 1];
-  int64_t j;
-  __device__ void init(const MttkrpArgs& a, int64_t j0) {
-    j = j0;
-    uint32_t rem = (uint32_t)min(j0, a.J);
-#pragma unroll
-    for (int q = 0; q < kMaxOrder - 1; ++q) {
-      const uint32_t d = (uint32_t)a.odim[q];
-      idx[q] = rem % d;
-      rem /= d;
-    }
-  }
-  __device__ void advance(const MttkrpArgs& a, int step) {
-    j += step;
-    idx[0] += step;
-    while (idx[0] >= (uint32_t)a.odim[0]) {
-      idx[0] -= a.odim[0];
-      if (++idx[1] >= (uint32_t)a.odim[1]) {
-        idx[1] = 0;
-        ++idx[2];
-      }
-    }
-  }
-};
+// LDS rows of 32 bf16 (four 16-byte chunks) with the chunk index XOR-ed by
+// g(row) = ((row >> 1) mod 4) ^ ((row >> 3) mod 2): the fragment reads (lanes of a
+// 16-lane group on 16 consecutive rows, one chunk) and the staging writes
+// (4 consecutive lanes per row, all four chunks) then hit distinct banks,
+// both for 64 four-byte banks served 16 lanes at a time and for 32 banks
+// served 8 lanes at a time (checked exhaustively on the host).
+// (g depends on row mod 16 only, so a fragment row's chunk follows from its lane.)
+__device__ __forceinline__ int swz(int row) { return ((row >> 1) & 3) ^ ((row >> 3) & 1); }
 
-
-template <int WM, int WN, int TM, int TN, int NTERM, int NO>
+// BRES: the block's B operand (its columns of U_L, all ilp rows) is loaded
+// into dynamic LDS once and stays there (U_L is the same for every wrap), so
+// a step streams only the tensor slab; otherwise B is staged per step like A.
+template <int WM, int WN, int TM, int TN, int NTERM, int NH, bool BRES>
 __global__ void __launch_bounds__(64 * WM * WN)
 k_mttkrp_bf(const MttkrpArgs a) {
   constexpr int NT = 64 * WM * WN;
   constexpr int BM = WM * TM * 16;
   constexpr int BN = WN * TN * 16;
   constexpr int BK = kBK;
-  constexpr int CH = BK / 8;                         // 8-column runs per row per step
+  constexpr int CH = BK / 8;                         // 8-K runs per row per step
   constexpr int AI = (BM * CH + NT - 1) / NT;        // A runs per thread
   constexpr int BI = (BN * CH + NT - 1) / NT;        // B runs per thread
   static_assert(NTERM == 2 || NTERM == 3, "terms");
-  static_assert(NO >= 1 && NO <= kMaxOrder - 1, "other modes");
+  static_assert(NH >= 0 && NH <= kMaxOrder - 2, "higher modes");
+  static_assert(NT >= BN, "one wrap scale per column and thread");
 
-  __shared__ __attribute__((aligned(16))) uint16_t As[2][NTERM][BM][kLdk];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][NTERM][BN][kLdk];
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][NTERM][BM][kBK];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[BRES ? 1 : 2][NTERM][BRES ? 1 : BN][kBK];
+  __shared__ double Ss[2][BN];   // wrap scales s(w, c) of the step's columns
+  // resident B: [term][K block of the wrap][column][32], swizzled chunks
+  extern __shared__ __attribute__((aligned(16))) uint16_t Bres[];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -118,7 +102,7 @@ k_mttkrp_bf(const MttkrpArgs a) {
 
   // Block -> (column tile, row tile, K chunk), XCD-aware as in the float64
   // kernel: each XCD receives a contiguous run of logical blocks, column
-  // tile fastest, so the blocks sharing one tensor slice share an L2.
+  // tile fastest, so the blocks sharing one tensor slab share an L2.
   const int total = gridDim.x;
   int logical = blockIdx.x;
   const int per_xcd = total / kXcds;
@@ -128,105 +112,97 @@ k_mttkrp_bf(const MttkrpArgs a) {
   const int split = logical / (a.ntiles * a.mtiles);
   const int i0 = mt * BM;
   const int c0 = nt * BN;
-  const int64_t kbeg = (int64_t)split * a.kchunk;
-  const int64_t kend = min(kbeg + a.kchunk, a.J);
-  const int nsteps = kend > kbeg ? (int)((kend - kbeg + BK - 1) / BK) : 0;
+  // K chunk: whole wraps [wbeg, wend); steps of BK within each wrap
+  const int64_t wbeg = (int64_t)split * a.kchunk;
+  const int64_t wend = min(wbeg + a.kchunk, a.wraps);
+  const int sw = a.ilp / BK;                                  // steps per wrap
+  const int nsteps = wend > wbeg ? (int)((wend - wbeg) * sw) : 0;
+  const uint32_t kbase = (uint32_t)(wbeg * a.ilp);            // first padded K of the chunk
 
   const uint16_t* __restrict__ Tp = static_cast<const uint16_t*>(a.T);
+  const uint16_t* __restrict__ Up = a.ut;
 
   // A runs: item e = tid + NT*u -> row e / CH, run e % CH (CH threads cover
-  // one row's 64 contiguous bytes per term).  Runs outside the tile or past
-  // the chunk read a clamped address and are not masked: past the chunk they
-  // meet zero Khatri-Rao entries, and rows past I_n produce output rows that
-  // are never stored (a non-finite tensor entry therefore only affects its
-  // own output row, which is non-finite in the exact product too).
-  const uint16_t* __restrict__ Tt[NTERM];
-#pragma unroll
-  for (int t = 0; t < NTERM; ++t) Tt[t] = Tp + (int64_t)t * a.plane;
-  // B runs: item e -> column e % BN (consecutive threads, consecutive
-  // columns: coalesced factor loads), run e / BN.
-  Walk wb[BI];
-#pragma unroll
-  for (int u = 0; u < BI; ++u) wb[u].init(a, kbeg + 8 * ((tid + NT * u) / BN));
-  const uint32_t ldc = (uint32_t)a.ldc;
+  // one row's 64 contiguous bytes per term).  B runs likewise: column e / CH,
+  // run e % CH.  Items outside the tile, and steps past the chunk, read a
+  // clamped address: rows past I_n and columns past ldc produce outputs that
+  // are never stored, and steps past the chunk are never computed.  Element
+  // offsets within a plane are below 2^31 (checked at init).
 
-  // Registers of the steps in flight, two stages indexed by a compile-time
-  // stage number: the loads of a step are issued two steps before its store
-  // (one wavefront per SIMD hides no latency by switching, so the distance
-  // has to come from the schedule).
   u32x4 ra[2][AI][NTERM];
-  float rlow[2][BI][8];        // the lowest other mode's 8 entries
-  float rhigh[2][BI][NO];      // the higher modes' entries (fast path)
-  bool bfast[2][BI], bok[2][BI];
+  u32x4 rb[2][BI][NTERM];
+  double rs[2][NH > 0 ? NH : 1];   // higher modes' entries of the step's wrap, one column per thread
   using S0_t = std::integral_constant<int, 0>;
   using S1_t = std::integral_constant<int, 1>;
 
+  // Wrap of the next step to load (loads run in step order): its index lw,
+  // the step within it lin, and its multi-index over the higher modes
+  // (lowest fastest), all uniform.
+  int64_t lw = wbeg;
+  int lin = 0;
+  uint32_t hidx[NH > 0 ? NH : 1];
+  {
+    uint32_t rem = (uint32_t)min(wbeg, a.wraps);
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      hidx[h] = rem % (uint32_t)a.hdim[h];
+      rem /= (uint32_t)a.hdim[h];
+    }
+  }
+  // column whose wrap scale this thread fetches (every thread loads, so the
+  // loads of a step are unconditional and their count is fixed)
+  const int scl = tid % BN;
+  const uint32_t scol = c0 + scl < a.ldc ? (uint32_t)(c0 + scl) : 0u;
+
+  // Every load of a step is unconditional (no branch around a load), so the
+  // wait before a step's store covers only that step's loads.
   auto load_step = [&](auto P, int s) __attribute__((always_inline)) {
     constexpr int p = decltype(P)::value;
-    const int64_t j0 = kbeg + (int64_t)s * BK;
+    const bool sok = s < nsteps;
+    // K blocks of 32: the step's slice of every row is contiguous
+    const uint32_t kb = kbase / BK + (uint32_t)s;                    // K block of the step
+    const uint32_t jb = (uint32_t)lin;                               // its low-mode block
 #pragma unroll
     for (int u = 0; u < AI; ++u) {
       const int e = tid + NT * u;
       const int row = e / CH, run = e % CH;
-      const int64_t j = j0 + 8 * run;
-      const bool ok = e < BM * CH && i0 + row < a.M && j < kend;
-      // element offset within a plane: below 2^31 (checked at init)
-      const uint32_t at = ok ? (uint32_t)(i0 + row) * (uint32_t)a.ldt + (uint32_t)j : 0u;
+      const bool ok = sok && e < BM * CH && i0 + row < a.M;
+      const uint32_t at = ok ? (kb * (uint32_t)a.M + (uint32_t)(i0 + row)) * BK + 8u * run : 0u;
 #pragma unroll
-      for (int t = 0; t < NTERM; ++t) ra[p][u][t] = *reinterpret_cast<const u32x4*>(Tt[t] + at);
+      for (int t = 0; t < NTERM; ++t)
+        ra[p][u][t] = *reinterpret_cast<const u32x4*>(Tp + (int64_t)t * a.plane + at);
     }
+    if constexpr (!BRES) {
 #pragma unroll
-    for (int u = 0; u < BI; ++u) {
-      const int e = tid + NT * u;
-      const int col = c0 + e % BN;
-      const Walk& w = wb[u];
-      const bool ok = e < BN * CH && col < a.ldc && w.j < kend;
-      bok[p][u] = ok;
-      // fast path: the run neither wraps the lowest mode nor crosses kend
-      const bool fast = ok && w.idx[0] + 8 <= (uint32_t)a.odim[0] && w.j + 8 <= kend;
-      bfast[p][u] = fast;
-      // float32 factor copies, 32-bit element offsets (below 2^31, checked
-      // at init); rows i_low .. i_low+7 exist on the fast path, row 0 is read
-      // eight times otherwise
-      const uint32_t cc = ok ? (uint32_t)col : 0u;
-      const uint32_t step = fast ? ldc : 0u;
-      uint32_t o0 = (fast ? w.idx[0] : 0u) * ldc + cc;
+      for (int u = 0; u < BI; ++u) {
+        const int e = tid + NT * u;
+        const int cl = e / CH, run = e % CH;
+        const bool ok = sok && e < BN * CH && c0 + cl < a.ldc;
+        const uint32_t at = ok ? (jb * (uint32_t)a.ldc + (uint32_t)(c0 + cl)) * BK + 8u * run : 0u;
 #pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        rlow[p][u][v] = a.oUf[0][o0];
-        o0 += step;
+        for (int t = 0; t < NTERM; ++t)
+          rb[p][u][t] = *reinterpret_cast<const u32x4*>(Up + (int64_t)t * a.ut_plane + at);
       }
+    }
+    const bool wok = sok && lw < a.wraps;
 #pragma unroll
-      for (int q = 1; q < NO; ++q) rhigh[p][u][q] = a.oUf[q][(ok ? w.idx[q] : 0u) * ldc + cc];
+    for (int h = 0; h < NH; ++h)
+      rs[p][h] = a.hU[h][(wok ? hidx[h] : 0u) * (uint32_t)a.ldc + scol];
+    if (++lin == sw) {
+      lin = 0;
+      ++lw;
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        if (++hidx[h] < (uint32_t)a.hdim[h]) break;
+        hidx[h] = 0;
+      }
     }
   };
 
-  // The store of a step, in two parts.  store_main writes the tensor runs
-  // and every Khatri-Rao run by the run formula (the higher modes' product
-  // times the 8 entries of the lowest mode), branch-free so that it can be
-  // interleaved with the matrix instructions; store_fix then rewrites, entry
-  // by entry, the runs the formula does not cover (runs that wrap the lowest
-  // mode, end the chunk or lie outside the tile) -- the same thread's later
-  // LDS write wins.
-  auto store_run = [&](float (&f)[8], int buf, int cl, int run) __attribute__((always_inline)) {
-#pragma unroll
-    for (int t = 0; t < NTERM; ++t) {
-      uint32_t wds[4];
-#pragma unroll
-      for (int v = 0; v < 8; v += 2) {
-        // round-to-nearest-even conversion of two entries; the remainders
-        // are exact in float32
-        const __bf16 h0 = (__bf16)f[v];
-        const __bf16 h1 = (__bf16)f[v + 1];
-        wds[v / 2] = (uint32_t)__builtin_bit_cast(uint16_t, h0) |
-                     ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
-        f[v] -= (float)h0;
-        f[v + 1] -= (float)h1;
-      }
-      *reinterpret_cast<u32x4*>(&Bs[buf][t][cl][8 * run]) = u32x4{wds[0], wds[1], wds[2], wds[3]};
-    }
-  };
-  auto store_main = [&](auto P, int buf) __attribute__((always_inline)) {
+  // The store of a step: both operands copied to LDS as loaded (swizzled
+  // chunks), and the step's wrap scales s(w, c) = product of the higher
+  // modes' entries, highest mode first (the order of Eq. (1)).
+  auto store_step = [&](auto P, int buf) __attribute__((always_inline)) {
     constexpr int p = decltype(P)::value;
 #pragma unroll
     for (int u = 0; u < AI; ++u) {
@@ -234,50 +210,26 @@ k_mttkrp_bf(const MttkrpArgs a) {
       if (AI * NT == BM * CH || e < BM * CH) {
         const int row = e / CH, run = e % CH;
 #pragma unroll
-        for (int t = 0; t < NTERM; ++t) *reinterpret_cast<u32x4*>(&As[buf][t][row][8 * run]) = ra[p][u][t];
+        for (int t = 0; t < NTERM; ++t)
+          *reinterpret_cast<u32x4*>(&As[buf][t][row][8 * (run ^ swz(row))]) = ra[p][u][t];
       }
     }
+    if constexpr (!BRES) {
 #pragma unroll
-    for (int u = 0; u < BI; ++u) {
-      const int e = tid + NT * u;
-      if (BI * NT == BN * CH || e < BN * CH) {
-        const int cl = e % BN, run = e / BN;
-        float f[8];
-        float hi = 1.f;
+      for (int u = 0; u < BI; ++u) {
+        const int e = tid + NT * u;
+        if (BI * NT == BN * CH || e < BN * CH) {
+          const int cl = e / CH, run = e % CH;
 #pragma unroll
-        for (int q = NO - 1; q >= 1; --q) hi = (q == NO - 1) ? rhigh[p][u][q] : hi * rhigh[p][u][q];
-#pragma unroll
-        for (int v = 0; v < 8; ++v) f[v] = NO == 1 ? rlow[p][u][v] : hi * rlow[p][u][v];
-        store_run(f, buf, cl, run);
-      }
-    }
-  };
-  auto store_fix = [&](auto P, int buf, int sdata) __attribute__((always_inline)) {
-    constexpr int p = decltype(P)::value;
-#pragma unroll
-    for (int u = 0; u < BI; ++u) {
-      const int e = tid + NT * u;
-      if (e >= BN * CH || bfast[p][u]) continue;
-      const int cl = e % BN, run = e / BN;
-      float f[8];
-      Walk w;
-      w.init(a, kbeg + (int64_t)sdata * BK + 8 * run);
-      const int col = c0 + cl;
-#pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        float x = 0.f;
-        if (bok[p][u] && w.j < kend) {
-#pragma unroll
-          for (int q = NO - 1; q >= 0; --q) {
-            const float y = a.oUf[q][w.idx[q] * ldc + (uint32_t)col];
-            x = (q == NO - 1) ? y : x * y;
-          }
+          for (int t = 0; t < NTERM; ++t)
+            *reinterpret_cast<u32x4*>(&Bs[buf][t][cl][8 * (run ^ swz(cl))]) = rb[p][u][t];
         }
-        f[v] = x;
-        w.advance(a, 1);
       }
-      store_run(f, buf, cl, run);
     }
+    double v = 1.0;
+#pragma unroll
+    for (int h = NH - 1; h >= 0; --h) v = (h == NH - 1) ? rs[p][h] : v * rs[p][h];
+    Ss[buf][scl] = v;
   };
 
   v4f accf[TM][TN];
@@ -294,32 +246,37 @@ k_mttkrp_bf(const MttkrpArgs a) {
   // stage of parity (s+1)&1 holds step s+1 and the other stage step s+2
   // (loads possibly in flight).  Step s computes from LDS, stores step s+1
   // into the other buffer, synchronises, and reuses the freed stage for the
-  // loads of step s+3.  Loads past the chunk fetch clamped addresses and are
-  // masked (zero Khatri-Rao entries), so they are issued unconditionally.
-  if (nsteps > 0) {
-    load_step(S0_t{}, 0);
-    store_main(S0_t{}, 0);
-    store_fix(S0_t{}, 0, 0);
-  }
-  __syncthreads();
-  auto advance_all = [&]() __attribute__((always_inline)) {
+  // loads of step s+3.
+  if constexpr (BRES) {
+    // every K block of the wrap, this block's columns (past ldc: clamped,
+    // their outputs are never stored)
+    const int items = sw * BN * CH;
+    for (int it = tid; it < items; it += NT) {
+      const int jb = it / (BN * CH);
+      const int rem = it - jb * (BN * CH);
+      const int cl = rem / CH, run = rem % CH;
+      const uint32_t at = c0 + cl < a.ldc ? ((uint32_t)jb * (uint32_t)a.ldc + (uint32_t)(c0 + cl)) * BK + 8u * run : 0u;
 #pragma unroll
-    for (int u = 0; u < BI; ++u) wb[u].advance(a, BK);
-  };
-  advance_all();
+      for (int t = 0; t < NTERM; ++t)
+        *reinterpret_cast<u32x4*>(&Bres[(((int64_t)t * sw + jb) * BN + cl) * BK + 8 * (run ^ swz(cl))]) =
+            *reinterpret_cast<const u32x4*>(Up + (int64_t)t * a.ut_plane + at);
+    }
+  }
+  load_step(S0_t{}, 0);
+  store_step(S0_t{}, 0);
+  __syncthreads();
   load_step(S1_t{}, 1);
-  advance_all();
   load_step(S0_t{}, 2);
 
   const int arow = wm * TM * 16 + (lane & 15);
   const int bcol = wn * TN * 16 + (lane & 15);
-  const int kq = 8 * (lane >> 4);
-  int since_flush = 0;
-  // one step; stage P holds step s+1 and receives step s+3 afterwards
+  const int kq = 8 * ((lane >> 4) ^ swz(lane & 15));   // fragment rows are 16-aligned
+  int in_wrap = 0;        // steps of the current wrap done
+  int since_flush = 0;    // steps accumulated in float32
   constexpr int NPROD = NTERM == 3 ? 6 : 3;
   constexpr int NMF = TM * TN * NPROD;            // matrix instructions per step
   constexpr int NRD = NTERM * (TN + TM);          // fragment reads per step
-  constexpr int NWR = NTERM * (AI + BI);          // LDS writes of the store
+  constexpr int NWR = NTERM * (AI + (BRES ? 0 : BI));   // LDS writes of the store
   auto step = [&](int s, auto P) __attribute__((always_inline)) {
     const int buf = s & 1;
     __builtin_amdgcn_sched_barrier(0);
@@ -328,7 +285,8 @@ k_mttkrp_bf(const MttkrpArgs a) {
     for (int t = 0; t < NTERM; ++t)
 #pragma unroll
       for (int y = 0; y < TN; ++y)
-        bfr[t][y] = *reinterpret_cast<const bf16x8*>(&Bs[buf][t][bcol + y * 16][kq]);
+        bfr[t][y] = BRES ? *reinterpret_cast<const bf16x8*>(&Bres[(((int64_t)t * sw + in_wrap) * BN + bcol + y * 16) * BK + kq])
+                         : *reinterpret_cast<const bf16x8*>(&Bs[buf][t][bcol + y * 16][kq]);
 #pragma unroll
     for (int x = 0; x < TM; ++x) {
       bf16x8 af[NTERM];
@@ -350,44 +308,53 @@ k_mttkrp_bf(const MttkrpArgs a) {
       }
     }
     // the next step's store (the other LDS buffer, free since the last
-    // barrier) interleaved with the matrix instructions: the fragment reads
-    // first, then each matrix instruction followed by a few vector
-    // instructions, the LDS writes spread over the step
-    store_main(P, buf ^ 1);
+    // barrier) interleaved with the matrix instructions
+    store_step(P, buf ^ 1);
     __builtin_amdgcn_sched_group_barrier(0x100, NRD, 0);       // fragment reads
 #pragma unroll
     for (int i = 0; i < NMF; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);       // matrix
-      __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);       // vector ALU
       if (i % (NMF / NWR > 0 ? NMF / NWR : 1) == 0)
         __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);     // LDS write
     }
     __builtin_amdgcn_sched_barrier(0);
-    store_fix(P, buf ^ 1, s + 1);
-    since_flush += BK;
-    if (since_flush >= kFlushK) {
+    ++in_wrap;
+    ++since_flush;
+    const bool wrap_end = in_wrap == sw;
+    if (wrap_end || since_flush == kFlushSteps) {
+      // the wrap's float32 sums, scaled by its Khatri-Rao factor, into float64
+      double sc[TN];
+#pragma unroll
+      for (int y = 0; y < TN; ++y) sc[y] = Ss[buf][bcol + y * 16];
 #pragma unroll
       for (int x = 0; x < TM; ++x)
 #pragma unroll
         for (int y = 0; y < TN; ++y)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            acc[x][y][r] += (double)accf[x][y][r];
+            acc[x][y][r] += sc[y] * (double)accf[x][y][r];
             accf[x][y][r] = 0.f;
           }
       since_flush = 0;
     }
+    if (wrap_end) in_wrap = 0;
     __syncthreads();
-    advance_all();
     load_step(P, s + 3);
   };
-  for (int s = 0; s < nsteps; s += 2) {
+  // Pairs of steps (stage parity is a compile-time constant) with no
+  // conditional step inside the loop, so the load count between a step's
+  // loads and its store is the same on every iteration; an odd last step
+  // runs after the loop.
+  int s = 0;
+  for (; s + 1 < nsteps; s += 2) {
     step(s, S1_t{});
-    if (s + 1 < nsteps) step(s + 1, S0_t{});
+    step(s + 1, S0_t{});
   }
+  if (s < nsteps) step(s, S1_t{});
 
   // Epilogue: v_mfma_f32_16x16x32_bf16 leaves row 4*(l/16)+r, column l%16
-  // of its 16x16 tile in lane l, element r.
+  // of its 16x16 tile in lane l, element r.  (Every chunk ends on a wrap
+  // boundary, so the float32 accumulators are empty here.)
   double* __restrict__ out = a.partial + (int64_t)split * a.M * a.ldc;
 #pragma unroll
   for (int x = 0; x < TM; ++x)
@@ -397,28 +364,46 @@ k_mttkrp_bf(const MttkrpArgs a) {
       for (int r = 0; r < 4; ++r) {
         const int row = i0 + wm * TM * 16 + x * 16 + 4 * (lane >> 4) + r;
         const int col = c0 + wn * TN * 16 + y * 16 + (lane & 15);
-        const double v = acc[x][y][r] + (double)accf[x][y][r];
-        if (row < a.M && col < a.ldc) out[(int64_t)row * a.ldc + col] = v;
+        if (row < a.M && col < a.ldc) out[(int64_t)row * a.ldc + col] = acc[x][y][r];
       }
 }
 
+constexpr size_t kLdsBytes = 160 * 1024;   // LDS per compute unit on gfx950
+
 template <int WM, int WN, int TM, int TN, int NTERM>
 hipError_t launch_bf(const MttkrpArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (a.ilp <= 0 || a.ilp % kBK != 0 || a.nh != a.nother - 1) return hipErrorInvalidValue;
+  constexpr int BM = WM * TM * 16, BN = WN * TN * 16;
   const dim3 grid(a.mtiles * a.ntiles * a.splits);
   const dim3 block(64 * WM * WN);
+  // B resident when it fits next to the static tiles
+  constexpr size_t fixed = (size_t)2 * NTERM * BM * kBK * 2 + (size_t)2 * BN * 8 + NTERM * kBK * 2;
+  const size_t bres = (size_t)NTERM * BN * a.ilp * 2;
+  const bool resident = fixed + bres <= kLdsBytes;
   // with events, the dispatch stamps them itself
-  auto go = [&](auto kernel) {
+  auto go = [&](auto kernel, size_t dyn) -> hipError_t {
+    if (dyn > 0) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+      if (e != hipSuccess) return e;
+    }
     if (e0 || e1)
-      hipExtLaunchKernelGGL(kernel, grid, block, 0, s, e0, e1, 0, a);
+      hipExtLaunchKernelGGL(kernel, grid, block, dyn, s, e0, e1, 0, a);
     else
-      hipLaunchKernelGGL(kernel, grid, block, 0, s, a);
+      hipLaunchKernelGGL(kernel, grid, block, dyn, s, a);
+    return hipSuccess;
   };
-  switch (a.nother) {
-    case 1: go(k_mttkrp_bf<WM, WN, TM, TN, NTERM, 1>); break;
-    case 2: go(k_mttkrp_bf<WM, WN, TM, TN, NTERM, 2>); break;
-    case 3: go(k_mttkrp_bf<WM, WN, TM, TN, NTERM, 3>); break;
+  hipError_t e = hipErrorInvalidValue;
+  switch (a.nh * 2 + (resident ? 1 : 0)) {
+    case 0: e = go(k_mttkrp_bf<WM, WN, TM, TN, NTERM, 0, false>, 0); break;
+    case 1: e = go(k_mttkrp_bf<WM, WN, TM, TN, NTERM, 0, true>, bres); break;
+    case 2: e = go(k_mttkrp_bf<WM, WN, TM, TN, NTERM, 1, false>, 0); break;
+    case 3: e = go(k_mttkrp_bf<WM, WN, TM, TN, NTERM, 1, true>, bres); break;
+    case 4: e = go(k_mttkrp_bf<WM, WN, TM, TN, NTERM, 2, false>, 0); break;
+    case 5: e = go(k_mttkrp_bf<WM, WN, TM, TN, NTERM, 2, true>, bres); break;
     default: return hipErrorInvalidValue;
   }
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
@@ -437,6 +422,8 @@ const std::vector<MttkrpVariant>& mttkrp_split_variants() {
       JKC_BF_VARIANT(1, 4, 7, 2, 2),   // 112 x 128
       JKC_BF_VARIANT(1, 4, 5, 2, 2),   // 80 x 128
       JKC_BF_VARIANT(2, 2, 2, 2, 2),   // 64 x 64
+      JKC_BF_VARIANT(2, 4, 4, 2, 2),   // 128 x 128, 8 wavefronts
+      JKC_BF_VARIANT(4, 2, 4, 2, 2),   // 256 x 64, 8 wavefronts
   };
   return v;
 }
@@ -448,6 +435,8 @@ const std::vector<MttkrpVariant>& mttkrp_split3_variants() {
       JKC_BF_VARIANT(1, 4, 7, 2, 3),   // 112 x 128
       JKC_BF_VARIANT(1, 4, 5, 2, 3),   // 80 x 128
       JKC_BF_VARIANT(2, 2, 2, 2, 3),   // 64 x 64
+      JKC_BF_VARIANT(2, 4, 4, 2, 3),   // 128 x 128, 8 wavefronts
+      JKC_BF_VARIANT(4, 2, 4, 2, 3),   // 256 x 64, 8 wavefronts
   };
   return v;
 }

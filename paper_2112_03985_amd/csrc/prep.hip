@@ -64,13 +64,15 @@ __device__ inline double bf16_to_double(uint16_t h) {
 }
 
 // x = t_1 + t_2 + ... : t_1 = bf16(x), t_2 = bf16(x - t_1), ... (each
-// remainder exact in float64), plane t at planes + t * n.
-// One thread per element (i, j) of the mode-n unfolding, row-major with
-// pitch ldt; column j maps to the other modes' indices lowest-first (Eq.
-// (3)).  Padding columns j >= J are zero.
+// remainder exact in float64), term t at planes + t * (plane size).
+// The mode-n unfolding with its columns ordered k = jl + ilp * w (low-mode
+// index jl, zero for jl >= I_low; wrap w over the other modes, lowest
+// fastest), stored in K blocks of 32: element (i, k) at
+// ((k / 32) * I_n + i) * 32 + k % 32, so the 32-K slice of every row is
+// one contiguous run of I_n * 64 bytes.  One thread per element.
 __global__ void k_split_unfold(const void* src, int32_t src_f32, int32_t N, int64_t d0,
-                               int64_t d1, int64_t d2, int64_t d3, int32_t n, int64_t ldt,
-                               int32_t nterm, uint16_t* planes) {
+                               int64_t d1, int64_t d2, int64_t d3, int32_t n, int32_t low,
+                               int32_t ilp, int32_t nterm, uint16_t* planes) {
   const int64_t dims[4] = {d0, d1, d2, d3};
   int64_t stride[4];
   int64_t P = 1;
@@ -79,17 +81,22 @@ __global__ void k_split_unfold(const void* src, int32_t src_f32, int32_t N, int6
     if (m < N) P *= dims[m];
   }
   const int64_t I = dims[n];
-  const int64_t J = P / I;
-  const int64_t total = I * ldt;
+  const int64_t wraps = P / (I * dims[low]);
+  const int64_t total = I * (int64_t)ilp * wraps;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e / ldt;
-    const int64_t j = e - i * ldt;
+    const int64_t kk = e & 31;
+    const int64_t q = e >> 5;
+    const int64_t kb = q / I;
+    const int64_t i = q - kb * I;
+    const int64_t k = kb * 32 + kk;
+    const int64_t w = k / ilp;
+    const int64_t jl = k - w * ilp;
     double x = 0.0;
-    if (j < J) {
-      int64_t rem = j, off = i * stride[n];
+    if (jl < dims[low]) {
+      int64_t rem = w, off = i * stride[n] + jl * stride[low];
       for (int m = 0; m < N; ++m) {
-        if (m == n) continue;
+        if (m == n || m == low) continue;
         off += (rem % dims[m]) * stride[m];
         rem /= dims[m];
       }
@@ -98,6 +105,28 @@ __global__ void k_split_unfold(const void* src, int32_t src_f32, int32_t N, int6
     for (int t = 0; t < nterm; ++t) {
       const uint16_t h = bf16_rne(x);
       planes[(int64_t)t * total + e] = h;
+      x -= bf16_to_double(h);
+    }
+  }
+}
+
+// The low mode's factor U (rows x ldc float64) as nterm bfloat16 terms, in
+// K blocks of 32 rows: term t of U(j, c) at out + t * ldc * ilp +
+// ((j / 32) * ldc + c) * 32 + j % 32, zero for rows <= j < ilp.
+__global__ void k_split_factor_t(const double* U, int32_t rows, int32_t ldc, int32_t ilp,
+                                 int32_t nterm, uint16_t* out) {
+  const int64_t total = (int64_t)ldc * ilp;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t jj = e & 31;
+    const int64_t q = e >> 5;
+    const int64_t jb = q / ldc;
+    const int64_t c = q - jb * ldc;
+    const int64_t j = jb * 32 + jj;
+    double x = j < rows ? U[j * ldc + c] : 0.0;
+    for (int t = 0; t < nterm; ++t) {
+      const uint16_t h = bf16_rne(x);
+      out[(int64_t)t * total + e] = h;
       x -= bf16_to_double(h);
     }
   }
@@ -281,24 +310,22 @@ hipError_t launch_copy_tensor(const void* src, int32_t src_f32, void* dst, int64
   return hipGetLastError();
 }
 
-__global__ void k_to_f32(const double* src, int64_t n, float* dst) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x)
-    dst[e] = (float)src[e];
-}
-
-hipError_t launch_to_f32(const double* src, int64_t n, float* dst, hipStream_t s) {
-  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(256), 0, s, src, n, dst);
+hipError_t launch_split_unfold(const void* src, int32_t src_f32, int32_t N, const int64_t* dims,
+                               int32_t n, int32_t low, int32_t ilp, int32_t nterm,
+                               uint16_t* planes, hipStream_t s) {
+  int64_t P = 1;
+  for (int m = 0; m < N; ++m) P *= dims[m];
+  const int64_t total = dims[n] * (int64_t)ilp * (P / (dims[n] * dims[low]));
+  hipLaunchKernelGGL(k_split_unfold, dim3(grid_for(total)), dim3(256), 0, s, src, src_f32, N,
+                     dims[0], N > 1 ? dims[1] : 1, N > 2 ? dims[2] : 1, N > 3 ? dims[3] : 1, n,
+                     low, ilp, nterm, planes);
   return hipGetLastError();
 }
 
-hipError_t launch_split_unfold(const void* src, int32_t src_f32, int32_t N, const int64_t* dims,
-                               int32_t n, int64_t ldt, int32_t nterm, uint16_t* planes,
-                               hipStream_t s) {
-  const int64_t total = dims[n] * ldt;
-  hipLaunchKernelGGL(k_split_unfold, dim3(grid_for(total)), dim3(256), 0, s, src, src_f32, N,
-                     dims[0], N > 1 ? dims[1] : 1, N > 2 ? dims[2] : 1, N > 3 ? dims[3] : 1, n,
-                     ldt, nterm, planes);
+hipError_t launch_split_factor_t(const double* U, int32_t rows, int32_t ldc, int32_t ilp,
+                                 int32_t nterm, uint16_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_split_factor_t, dim3(grid_for((int64_t)ldc * ilp)), dim3(256), 0, s, U,
+                     rows, ldc, ilp, nterm, out);
   return hipGetLastError();
 }
 

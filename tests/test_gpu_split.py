@@ -32,21 +32,44 @@ def _bf16(x):
     return np.ldexp(np.round(m * 256.0) / 256.0, e)
 
 
+def _low_mode(dims, n):
+    """The other mode whose factor the split kernel splits into bfloat16
+    terms: the one whose size pads to a multiple of 32 with the least
+    relative waste, the larger size on ties (then the lower mode)."""
+    best = None
+    for m in range(len(dims)):
+        if m == n:
+            continue
+        if best is None:
+            best = m
+            continue
+        pm, pb = -(-dims[m] // 32) * 32, -(-dims[best] // 32) * 32
+        lhs, rhs = pm * dims[best], pb * dims[m]
+        if lhs < rhs or (lhs == rhs and dims[m] > dims[best]):
+            best = m
+    return best
+
+
 def _model_error_x3(wl, k, n):
     """Normwise error of the two-term, three-product representation computed
-    in exact (float64) arithmetic: the floor any implementation of it has."""
+    in exact (float64) arithmetic: the floor any implementation of it has.
+    The tensor and the low mode's factor are split into two bfloat16 terms;
+    the other factors enter the Khatri-Rao product exactly (float64)."""
     c = cols(wl, k)
     U = [np.array(u[:, c]) for u in wl.init]
     p = int(wl.left_out[k])
     if p >= 0:
         U[wl.sampled_mode][p] = 0.0
     Tn = oracle.unfold(np.asarray(wl.T, dtype=np.float64), n)
-    K = oracle.krp_excluding(U, n).astype(np.float32).astype(np.float64)
     M = Tn @ oracle.krp_excluding(U, n)
+    L = _low_mode(list(wl.dims), n)
+    Uh, Ul = list(U), list(U)
+    Uh[L] = _bf16(U[L])
+    Ul[L] = _bf16(U[L] - Uh[L])
     Th = _bf16(Tn)
     Tl = _bf16(Tn - Th)
-    Kh = _bf16(K)
-    Kl = _bf16(K - Kh)
+    Kh = oracle.krp_excluding(Uh, n)
+    Kl = oracle.krp_excluding(Ul, n)
     M3 = Th @ Kh + Th @ Kl + Tl @ Kh
     if n == wl.sampled_mode and p >= 0:
         M[p] = 0.0
