@@ -178,8 +178,9 @@ jkc_status jk_cals_get_status(jkc_ctx *ctx, double *err, double *fit,
  * the context's factors with lambda folded into the last mode (the
  * all-at-once formulation the paper cites in Sec. 2), and its gradient
  * dF/dU_n = U_n H_n - M_n for every mode (an all-mode MTTKRP: fused per
- * mode, or through the shared contraction of jk_cals_set_mttkrp_tree), with
- * the left-out rows of the sampled mode held at 0.  lambda is folded into the
+ * mode, through the shared contraction of jk_cals_set_mttkrp_tree, or in one
+ * pass over T, jk_cals_set_allmode), with the left-out rows of the sampled
+ * mode held at 0.  lambda is folded into the
  * last factor first (and reset to 1).  loss: device [K] (may be NULL).  The
  * gradients stay in the workspace for jk_cals_get_grad.  Asynchronous. */
 jkc_status jk_cals_loss_grad(jkc_ctx *ctx, double *loss);
@@ -289,6 +290,22 @@ jkc_status jk_cals_set_update_kernel(jkc_ctx *ctx, int32_t which);
  * is read twice instead of three times); jk_cals_mttkrp always runs the
  * fused MTTKRP.  Host only. */
 jkc_status jk_cals_set_mttkrp_tree(jkc_ctx *ctx, int32_t enable);
+
+/* All-mode MTTKRP of jk_cals_loss_grad / jk_cals_refine in one pass over the
+ * tensor (the gradient of the all-at-once CP loss, Sec. 2, needs every
+ * mode's MTTKRP at the same factors): a tile of T staged once feeds the
+ * fused MTTKRP of mode 0 and the mode-0 contraction Z = T x_0 U_0 on the
+ * float64 matrix cores, from which the other modes follow by per-column
+ * products -- 4 C P matrix-core flops for all modes instead of 2 N C P.
+ * Available for 3- and 4-way float64 problems with at most 256 rows in mode
+ * 0, a tensor below 2^31 bytes and a block that fits in LDS; the default
+ * where no shared contraction is held (4-way problems, 3-way problems whose W
+ * does not fit), where it is the faster path.  enable = 0 returns to the
+ * per-mode path (the shared contraction where held, else the fused MTTKRP of
+ * every mode).  Results agree up to rounding (summation order).
+ * JKC_EUNSUPPORTED for enable = 1 on other problems, EINVAL for other
+ * values.  Host only. */
+jkc_status jk_cals_set_allmode(jkc_ctx *ctx, int32_t enable);
 
 /* Replay multi-sweep runs of jk_cals_sweep from a HIP graph of one sweep,
  * captured on first use (enable = 1), or launch every kernel directly

@@ -95,6 +95,7 @@ def lib() -> ctypes.CDLL:
         "jk_cals_set_update_kernel": (I32, [VP, I32]),
         "jk_cals_set_sweep_graph": (I32, [VP, I32]),
         "jk_cals_set_mttkrp_tree": (I32, [VP, I32]),
+        "jk_cals_set_allmode": (I32, [VP, I32]),
         "jk_cals_profile": (I32, [VP, I32]),
         "jk_cals_profile_read": (I32, [VP, VP, VP]),
         "jk_cals_set_tiling": (I32, [VP, I32, I32, I32]),
@@ -404,6 +405,9 @@ class JkCals:
     def set_mttkrp_tree(self, enable: bool):
         _check(lib().jk_cals_set_mttkrp_tree(self.ctx, 1 if enable else 0))
 
+    def set_allmode(self, enable: bool):
+        _check(lib().jk_cals_set_allmode(self.ctx, 1 if enable else 0))
+
     def num_tilings(self) -> int:
         return int(lib().jk_cals_num_tilings(self.ctx))
 
@@ -486,6 +490,10 @@ def jk_cals_set_sweep_graph(ctx: JkCals, enable: bool):
 
 def jk_cals_set_mttkrp_tree(ctx: JkCals, enable: bool):
     return ctx.set_mttkrp_tree(enable)
+
+
+def jk_cals_set_allmode(ctx: JkCals, enable: bool):
+    return ctx.set_allmode(enable)
 
 
 def jk_cals_num_tilings(ctx: JkCals) -> int:

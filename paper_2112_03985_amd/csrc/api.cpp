@@ -49,6 +49,7 @@ jkc_status fail(jkc_status st, const std::string& msg) {
 
 constexpr int64_t kAlign = 256;
 constexpr int kNumCU = 256;
+constexpr int64_t kAllModeLds = 160 * 1024;   // LDS per compute unit on gfx950
 constexpr int kSliceChunks = 256;
 constexpr size_t kMaxTimedLaunches = 65536;
 
@@ -85,6 +86,11 @@ struct Plan {
   int split_max[kMaxOrder] = {1, 1, 1, 1};
   int64_t partial_doubles = 0;
   int64_t tree_rows = 0;   // rows of W (3-way float64 sweeps), 0 when not held
+  // one-pass all-mode MTTKRP of the gradient: fibers per step (0: not
+  // available), chunks of the last mode, doubles of its split partials
+  int allmode_bk = 0;
+  int allmode_nchunks = 0;
+  int64_t allmode_doubles = 0;
 
   struct Item {
     const char* name;
@@ -152,6 +158,7 @@ struct Plan {
     items.push_back({"colmap", (int64_t)ldc * 4});
     // shared partial contraction of a 3-way sweep
     items.push_back({"tree", tree_rows * ldc * 8});
+    items.push_back({"allmode", allmode_doubles * 8});
     total = 0;
     for (auto& it : items) total += align_up(std::max<int64_t>(it.bytes, 1), kAlign);
   }
@@ -266,6 +273,32 @@ jkc_status make_plan(const jkc_problem* prob, Plan* pl) {
       pl->dims[0] * pl->dims[1] < (int64_t(1) << 31) &&   // W's rows are 32-bit in the kernel
       pl->dims[0] * pl->dims[1] * (int64_t)pl->ldc * 8 <= tree_cap)
     pl->tree_rows = pl->dims[0] * pl->dims[1];
+  // one-pass all-mode MTTKRP: 3- and 4-way float64 problems with at most 256
+  // rows in mode 0 whose block fits in LDS; enough chunks of the last mode to
+  // give the chip about one block per compute unit
+  pl->allmode_bk = 0;
+  if ((pl->N == 3 || pl->N == 4) && pl->precision == JKC_FP64 && pl->dims[0] <= 256 &&
+      pl->dims[1] <= 65536 && pl->dims[2] <= 65536 &&
+      P * (pl->tensor_f32 ? 4 : 8) < (int64_t(1) << 31)) {   // 32-bit buffer offsets
+    const int nt = allmode_row_tiles((int)pl->dims[0]);
+    for (int bk : {16, 8})
+      if (allmode_has_kernel(nt, bk) &&
+          allmode_lds_bytes(nt * 16, bk, (int)pl->dims[1], (int)pl->dims[2], pl->N) <= kAllModeLds) {
+        pl->allmode_bk = bk;
+        break;
+      }
+    if (pl->allmode_bk > 0) {
+      const int64_t ntiles = (pl->ldc + kAllModeCols - 1) / kAllModeCols;
+      const int64_t last = pl->dims[pl->N - 1];
+      // (one block per compute unit at most: a second round of blocks
+      // would double the time)
+      const int64_t want = std::max<int64_t>(1, kNumCU / ntiles);
+      pl->allmode_nchunks = (int)std::min<int64_t>(last, want);
+      int64_t rows = 0;
+      for (int m = 0; m + 1 < pl->N; ++m) rows += pl->dims[m];
+      pl->allmode_doubles = pl->allmode_nchunks * rows * pl->ldc;
+    }
+  }
   pl->layout();
   return JKC_OK;
 }
@@ -837,8 +870,72 @@ jkc_status enqueue_fold_lambda(jkc_ctx* ctx) {
 }
 
 // All-mode gradient at the current factors (lambda folded), loss optional.
+// Loss and gradient assembly of every mode from the MTTKRPs held in
+// ctx->grad[n] (in place: the gradient overwrites its MTTKRP).
+jkc_status enqueue_grad_assemble(jkc_ctx* ctx, double* loss) {
+  for (int n = 0; n < ctx->N; ++n) {
+    GradArgs g{};
+    g.mt = ctx->table();
+    g.N = ctx->N;
+    g.n = n;
+    g.nhat = ctx->nhat;
+    g.In = (int32_t)ctx->dims[n];
+    g.ldc = ctx->ldc;
+    g.Mfull = ctx->grad[n];
+    g.U = ctx->U[n];
+    for (int m = 0; m < kMaxOrder; ++m) g.Gp[m] = ctx->G[m];
+    g.grad = ctx->grad[n];
+    g.normT2 = ctx->normT2;
+    g.loss = loss;
+    g.last_mode = (loss != nullptr && n == ctx->N - 1) ? 1 : 0;
+    JKC_HIP(launch_grad_assemble(g, ctx->stream));
+  }
+  return JKC_OK;
+}
+
+// All-mode MTTKRP in one pass over T (allmode.hip) into ctx->grad[n]: the
+// last mode written directly, modes 0 .. N-2 reduced from their per-chunk
+// partials in a fixed order.  Rows of the sampled mode's left-out samples
+// are left as computed: the gradient assembly holds them at 0 and their
+// factor rows are 0.
+jkc_status enqueue_allmode(jkc_ctx* ctx) {
+  AllModeArgs a{};
+  a.T = ctx->T;
+  a.tbytes = ctx->P * (ctx->tensor_f32 ? 4 : 8);
+  a.t_is_f32 = ctx->tensor_f32;
+  a.N = ctx->N;
+  for (int m = 0; m < kMaxOrder; ++m) {
+    a.dims[m] = m < ctx->N ? (int32_t)ctx->dims[m] : 1;
+    a.U[m] = m < ctx->N ? ctx->U[m] : nullptr;
+  }
+  a.ldc = ctx->ldc;
+  a.i0p = 16 * allmode_row_tiles((int)ctx->dims[0]);
+  a.bk = ctx->allmode_bk;
+  const int64_t last = ctx->dims[ctx->N - 1];
+  a.nchunks = ctx->allmode_nchunks;
+  a.chunk = (int32_t)((last + a.nchunks - 1) / a.nchunks);
+  a.nchunks = (int32_t)((last + a.chunk - 1) / a.chunk);
+  a.ntiles = (ctx->ldc + kAllModeCols - 1) / kAllModeCols;
+  int64_t off = 0;
+  for (int m = 0; m + 1 < ctx->N; ++m) {
+    a.part[m] = ctx->allmode_part + off;
+    off += (int64_t)a.nchunks * ctx->dims[m] * ctx->ldc;
+  }
+  a.out_last = ctx->grad[ctx->N - 1];
+  JKC_HIP(launch_allmode(a, ctx->stream));
+  for (int m = 0; m + 1 < ctx->N; ++m)
+    JKC_HIP(launch_reduce(a.part[m], a.nchunks, (int32_t)ctx->dims[m], ctx->ldc, ctx->ldc,
+                          ctx->left_out(), 0, ctx->grad[m], ctx->ldc, ctx->stream, nullptr));
+  return JKC_OK;
+}
+
 jkc_status enqueue_loss_grad(jkc_ctx* ctx, double* loss) {
   JKC_TRY(enqueue_fold_lambda(ctx));
+  if (ctx->use_allmode) {
+    ctx->tree_fresh = false;
+    JKC_TRY(enqueue_allmode(ctx));
+    return enqueue_grad_assemble(ctx, loss);
+  }
   // all-mode MTTKRP with the factors fixed: for 3-way float64 problems one
   // shared contraction W = T x_2 U_2 serves modes 0 and 1 (the tensor is read
   // twice instead of three times, two thirds of the matrix-core flops)
@@ -1043,6 +1140,14 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
   c.Wtree = static_cast<double*>(take(it++));
   c.tree_avail = pl.tree_rows > 0;
   c.use_tree = c.tree_avail;
+  c.allmode_part = static_cast<double*>(take(it++));
+  c.allmode_avail = pl.allmode_bk > 0;
+  // default where no shared contraction is held (4-way problems, 3-way
+  // problems whose W does not fit): measured faster than the per-mode fused
+  // MTTKRPs there, slower than the shared contraction for 3-way tensors
+  c.use_allmode = c.allmode_avail && !c.tree_avail;
+  c.allmode_bk = pl.allmode_bk;
+  c.allmode_nchunks = pl.allmode_nchunks;
 
   hipStream_t st = c.stream;
   // model tables (host vectors live in the context, so the copies are safe)
@@ -1612,6 +1717,18 @@ jkc_status jk_cals_set_mttkrp_tree(jkc_ctx* ctx, int32_t enable) {
   if (ctx->use_tree != (enable != 0)) drop_graph(ctx);
   ctx->use_tree = enable != 0;
   ctx->tree_fresh = false;
+  g_last_error.clear();
+  return JKC_OK;
+}
+
+jkc_status jk_cals_set_allmode(jkc_ctx* ctx, int32_t enable) {
+  JKC_TRY(check_ctx(ctx));
+  if (enable != 0 && enable != 1) return fail(JKC_EINVAL, "enable must be 0 or 1");
+  if (enable && !ctx->allmode_avail)
+    return fail(JKC_EUNSUPPORTED,
+                "the one-pass all-mode MTTKRP needs a 3- or 4-way float64 problem with at most 256 "
+                "rows in mode 0 whose block fits in LDS");
+  ctx->use_allmode = enable != 0;
   g_last_error.clear();
   return JKC_OK;
 }

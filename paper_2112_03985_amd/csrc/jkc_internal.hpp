@@ -215,6 +215,34 @@ hipError_t launch_remove_slice(const void* src, int32_t elem_bytes,
 hipError_t launch_count_active(const int32_t* status, int32_t K, int32_t* out,
                                hipStream_t s);
 
+// One-pass all-mode MTTKRP (allmode.hip): 3- and 4-way float64 problems
+// whose mode 0 has at most 256 rows.  Block (column tile of 32, chunk of
+// consecutive last-mode indices); modes 0 .. N-2 as split partials over the
+// chunks, the last mode written directly.
+struct AllModeArgs {
+  const void* T;
+  int64_t tbytes;           // bytes of T (below 2^31: 32-bit buffer offsets)
+  int32_t t_is_f32;
+  int32_t N;
+  int32_t dims[kMaxOrder];
+  const double* U[kMaxOrder];
+  int32_t ldc;
+  int32_t i0p;              // mode-0 rows padded to 16 * allmode_row_tiles(I0)
+  int32_t bk;               // fibers per step: 8 or 16
+  int32_t chunk;            // last-mode indices per chunk
+  int32_t nchunks;
+  int32_t ntiles;           // 32-column tiles
+  double* part[kMaxOrder - 1];   // [nchunks][I_m][ldc] for m = 0 .. N-2
+  double* out_last;         // [I_{N-1}][ldc]
+};
+constexpr int kAllModeCols = 32;
+int64_t allmode_lds_bytes(int i0p, int bk, int I1, int I2, int N);
+// Row tiles the compiled kernels offer for a mode-0 size I0 (0: none), and
+// whether a (row tiles, fibers per step) pair is compiled.
+int allmode_row_tiles(int I0);
+bool allmode_has_kernel(int nt, int bk);
+hipError_t launch_allmode(const AllModeArgs& a, hipStream_t s);
+
 struct GradArgs {
   ModelTable mt;
   int32_t N, n, nhat;
@@ -312,6 +340,12 @@ struct jkc_ctx {
   // Shared partial contraction of a 3-way float64 sweep (tree.hip):
   // W = T x_2 U_2, [I_0 I_1][ldc], computed at mode 0 and used by modes 0, 1
   double* Wtree = nullptr;
+  // One-pass all-mode MTTKRP of the loss gradient (allmode.hip)
+  bool allmode_avail = false;
+  bool use_allmode = false;
+  int32_t allmode_bk = 16;
+  int32_t allmode_nchunks = 1;
+  double* allmode_part = nullptr;
   bool tree_avail = false;       // the workspace holds W
   bool use_tree = false;
   bool tree_fresh = false;       // W matches U_2 of this sweep (host-side order)

@@ -138,6 +138,8 @@ def test_gradient_with_and_without_the_shared_contraction(spec):
     wl = synth.random_problem(seed, dims, ranks, lo, noise=0.1, sampled_mode=nh)
     say("tree gradient", seed)
     a, b = make_ctx(wl), make_ctx(wl)
+    for c in (a, b):
+        c.set_allmode(False)   # the per-mode paths (the one-pass kernel has its own tests)
     b.set_mttkrp_tree(False)
     la = torch.empty(wl.K, dtype=torch.float64, device="cuda")
     lb = torch.empty_like(la)
