@@ -62,6 +62,10 @@ def parse():
     ap.add_argument("--delete-d", type=int, default=1,
                     help="c2 only: delete-d jackknife over groups of d consecutive samples "
                          "(I/d submodels; the baselines are skipped)")
+    ap.add_argument("--gradient-path", default="default", choices=["default", "allmode", "per-mode"],
+                    help="c5: the all-mode MTTKRP of the refinement's gradient -- the library's "
+                         "default, the one-pass kernel (jk_cals_set_allmode 1), or the per-mode "
+                         "path (shared contraction / fused MTTKRPs)")
     ap.add_argument("--efficiency-sweep", action="store_true",
                     help="instead of the benchmark: fused MTTKRP efficiency against the column "
                          "count C on a 50x200x200 tensor (the analogue of the paper's Fig. 1); "
@@ -293,6 +297,8 @@ def main():
         else:
             ctx.sweep(sweeps)
         if refine_steps:
+            if args.gradient_path != "default":
+                ctx.set_allmode(args.gradient_path == "allmode")
             ctx.refine(refine_steps)
         return ctx
 
@@ -397,6 +403,29 @@ def main():
                                    "Khatri-Rao products, no split-K)",
                          "avg_launch_ms": round(w_ms, 5), "achieved": round(w_tf, 3),
                          "frac": round(w_tf / PEAK_FP64_TFLOPS, 4), "launches_per_sweep": 1}
+
+    if refine_steps:
+        # loss + gradient per call (fold, all-mode MTTKRP, gradient assembly)
+        # on the one-pass kernel and on the per-mode path, torch events
+        lg = {}
+        lbuf = torch.empty(K, dtype=torch.float64, device="cuda")
+        for path in ("allmode", "per-mode"):
+            try:
+                c.set_allmode(path == "allmode")
+            except jk.JkcError:
+                continue
+            c.loss_grad(lbuf)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(10):
+                c.loss_grad(lbuf)
+            e1.record()
+            torch.cuda.synchronize()
+            lg[path] = round(e0.elapsed_time(e1) / 10, 5)
+        out["loss_grad_call_ms"] = dict(lg, note="jk_cals_loss_grad per call; the all-mode "
+                                        "MTTKRP costs 4 C P matrix-core flops on the one-pass "
+                                        "kernel, the refinement ran on the '%s' path"
+                                        % args.gradient_path)
 
     # after the timed region: the MTTKRP with its split-K reduction (what a
     # caller of jk_cals_mttkrp gets), per mode, HIP events on the stream
