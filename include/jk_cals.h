@@ -322,7 +322,10 @@ int32_t jk_cals_num_tilings(jkc_ctx *ctx);
  * (clamped to 1 .. the context's limit) for `mode`.  Any tiling gives the
  * same result up to the order of the float64 sums.  JKC_EINVAL for a
  * buffer-load tiling (its description ends in "-buffer") when the tensor or
- * a multi-factor takes 2^31 bytes or more.  Host only. */
+ * a multi-factor takes 2^31 bytes or more, and for the narrow vector-ALU
+ * tiling ("valu-narrow": a streaming pass over T for problems of at most 16
+ * columns, the plain per-submodel ALS of Alg. 2) when C > 16 or mode 0 has
+ * more than 256 rows (128 with more than 8 columns).  Host only. */
 jkc_status jk_cals_set_tiling(jkc_ctx *ctx, int32_t mode, int32_t variant, int32_t splits);
 
 /* Kernel timing of the fused MTTKRP (the dominant kernel; Alg. 3, MTTKRP

@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libjkcals.so")
 
-SOURCES = ["api.cpp", "prep.hip", "update.hip", "mttkrp_f64.hip", "mttkrp_split.hip", "postprocess.hip", "tree.hip", "allmode.hip"]
+SOURCES = ["api.cpp", "prep.hip", "update.hip", "mttkrp_f64.hip", "mttkrp_split.hip", "postprocess.hip", "tree.hip", "allmode.hip", "mttkrp_narrow.hip"]
 
 ARCH = "gfx950"
 # -packed-fp32-ops: keep the compiler from forming packed float32 ops.

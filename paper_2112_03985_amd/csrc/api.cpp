@@ -172,7 +172,9 @@ int split_cap(int64_t rows, int64_t ldc, int64_t J) {
   const int64_t plane = rows * ldc * 8;
   const int64_t budget = std::max<int64_t>(128ll << 20, 4 * plane);
   int64_t s = budget / std::max<int64_t>(plane, 1);
-  s = std::min<int64_t>(s, 128);
+  // (16-column problems: small planes, and the narrow variant needs more
+  // chunks to fill the chip)
+  s = std::min<int64_t>(s, ldc <= 16 ? 512 : 128);
   s = std::min<int64_t>(s, std::max<int64_t>(1, J / 64));
   return (int)std::max<int64_t>(s, 1);
 }
@@ -310,13 +312,20 @@ struct ModeShape {
   int64_t M, J;
   int ncols, ldc, split_max;
   bool buf_ok;   // tensor and factors addressable with 32-bit byte offsets
+  int64_t i0 = 0;       // size of mode 0 (the fibers the narrow variant walks)
+  bool mode0 = false;   // the output mode is mode 0 (rows contiguous)
 };
 
 // Float64 kernels with buffer loads (instr bit 16) address the tensor and
 // the factors with 32-bit byte offsets: usable when each is below 2^31
 // bytes (with room for the walk past the end of the last K chunk).
 constexpr int64_t kBufLimit = (int64_t(1) << 31) - (int64_t(1) << 24);
-bool usable(const MttkrpVariant& x, const ModeShape& s) { return !(x.instr & 16) || s.buf_ok; }
+bool usable(const MttkrpVariant& x, const ModeShape& s) {
+  if (x.instr & kNarrowInstr)
+    return s.ldc == 16 && s.i0 > 0 && narrow_supports((int)std::min<int64_t>(s.i0, 1 << 20), s.ncols) &&
+           (s.mode0 ? s.M == s.i0 : true);
+  return !(x.instr & 16) || s.buf_ok;
+}
 
 Tiling make_tiling(const std::vector<MttkrpVariant>& vars, int v, const ModeShape& s, int splits) {
   Tiling t;
@@ -328,6 +337,14 @@ Tiling make_tiling(const std::vector<MttkrpVariant>& vars, int v, const ModeShap
 }
 
 int default_splits(const Tiling& t, const ModeShape& s) {
+  if (t.instr & kNarrowInstr) {
+    // about two blocks per compute unit, at least 16 fibers per chunk
+    const int64_t rt = s.mode0 ? 1 : (s.M + 3) / 4;
+    const int64_t fibers = s.mode0 ? s.J : s.J / std::max<int64_t>(s.i0, 1);
+    int64_t sp = (2 * kNumCU + rt - 1) / rt;
+    sp = std::min<int64_t>(sp, std::max<int64_t>(1, fibers / 16));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(sp, s.split_max));
+  }
   const int64_t tiles = ((s.M + t.bm() - 1) / t.bm()) * ((s.ncols + t.bn() - 1) / t.bn());
   // aim for two resident blocks per compute unit (one of 8 wavefronts)
   const int64_t want_blocks = (t.wm * t.wn >= 8 ? 1 : 2) * kNumCU;
@@ -340,6 +357,9 @@ int default_splits(const Tiling& t, const ModeShape& s) {
 // work, divided by how well one step's MFMA work hides its fixed load/barrier
 // cost and by how well the grid fills the chip, plus split-K partial traffic.
 double model_cost(const Tiling& t, const ModeShape& s) {
+  // the narrow variant streams the tensor once at the HBM rate; the
+  // matrix-core tilings pad 16 columns to their tile width
+  if (t.instr & kNarrowInstr) return 0.5;
   const int64_t mt = (s.M + t.bm() - 1) / t.bm();
   const int64_t nt = (s.ncols + t.bn() - 1) / t.bn();
   const double useful = (double)s.M * s.ncols;
@@ -386,6 +406,8 @@ ModeShape mode_shape(const jkc_ctx* ctx, int n, int split_max) {
   bool ok = ctx->P * (ctx->tensor_f32 ? 4 : 8) < kBufLimit;
   for (int m = 0; m < ctx->N; ++m) ok = ok && ctx->dims[m] * ctx->ldc * 8 < kBufLimit;
   s.buf_ok = ok;
+  s.i0 = ctx->nterm > 0 ? 0 : ctx->dims[0];   // float64 path only
+  s.mode0 = n == 0;
   return s;
 }
 
@@ -409,6 +431,7 @@ std::string describe_tiling(const Tiling& t, int precision) {
            precision == JKC_SPLIT_BF16X3 ? "bf16x3" : precision == JKC_SPLIT_BF16X6 ? "bf16x6" : "f64",
            t.variant, t.wm, t.wn, t.tm, t.tn, t.bk, t.splits,
            precision != JKC_FP64 ? "mfma16x16x32bf16"
+           : (t.instr & kNarrowInstr) ? "valu-narrow"
            : fam == 2            ? "mfma4x4x4-strips"
            : fam == 1            ? "mfma4x4x4-diagonal"
                                  : "mfma16x16x4",
@@ -500,10 +523,20 @@ void tune_store(const jkc_ctx* c, int n, const Tiling& t) {
 // ---------------------------------------------------------------------------
 // Launch helpers.
 // ---------------------------------------------------------------------------
+// Float64 tilings: the matrix-core variants, then the narrow vector-ALU one.
+const std::vector<MttkrpVariant>& f64_variants_all() {
+  static const std::vector<MttkrpVariant> v = [] {
+    std::vector<MttkrpVariant> x = mttkrp_f64_variants();
+    x.push_back(mttkrp_narrow_variant());
+    return x;
+  }();
+  return v;
+}
+
 const std::vector<MttkrpVariant>& variants_for(const jkc_ctx* ctx) {
   if (ctx->precision == JKC_SPLIT_BF16X3) return mttkrp_split_variants();
   if (ctx->precision == JKC_SPLIT_BF16X6) return mttkrp_split3_variants();
-  return mttkrp_f64_variants();
+  return f64_variants_all();
 }
 
 jkc_status launch_mttkrp_timed(jkc_ctx* ctx, const MttkrpArgs& a, const Tiling& t, int slot,
@@ -522,7 +555,8 @@ void chunking(const jkc_ctx* ctx, int n, const Tiling& t, int64_t* kchunk, int* 
     step = 1;
   } else {
     J = ctx->P / ctx->dims[n];
-    step = t.bk;
+    // the narrow variant's chunks are whole mode-0 fibers
+    step = ((t.instr & kNarrowInstr) && n != 0) ? ctx->dims[0] : t.bk;
   }
   int64_t kc = align_up((J + t.splits - 1) / t.splits, step);
   *kchunk = kc;
@@ -1754,7 +1788,10 @@ jkc_status jk_cals_set_tiling(jkc_ctx* ctx, int32_t mode, int32_t variant, int32
   if (splits < 1) return fail(JKC_EINVAL, "splits must be >= 1");
   const ModeShape shape = mode_shape(ctx, mode, ctx->split_max[mode]);
   if (!usable(vars[variant], shape))
-    return fail(JKC_EINVAL, "this tiling needs the tensor and every factor below 2^31 bytes");
+    return fail(JKC_EINVAL, (vars[variant].instr & kNarrowInstr)
+                                ? "the narrow tiling needs at most 16 columns (ldc 16) and mode 0 of "
+                                  "at most 256 rows (128 with more than 8 columns), float64 path"
+                                : "this tiling needs the tensor and every factor below 2^31 bytes");
   ctx->tiling[mode] = make_tiling(vars, variant, shape, splits);
   ctx->describe[mode] = describe_tiling(ctx->tiling[mode], ctx->precision);
   drop_graph(ctx);

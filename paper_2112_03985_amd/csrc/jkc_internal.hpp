@@ -33,7 +33,9 @@ struct Tiling {
   int variant = -1;   // index into the kernel table (precision specific)
   int wm = 0, wn = 0, tm = 0, tn = 0, bk = 0, instr = 0;
   int splits = 1;
-  int bm() const { return wm * tm * ((instr & 7) == 2 ? 4 : 16); }
+  // rows per block (the narrow variant: 4 output rows, one per wavefront,
+  // for modes other than 0)
+  int bm() const { return (instr & 32) ? 4 : wm * tm * ((instr & 7) == 2 ? 4 : 16); }
   int bn() const { return wn * tn * 16; }
 };
 
@@ -76,6 +78,13 @@ struct MttkrpVariant {
                // 8 when the step uses the interleaved instruction schedule
 };
 const std::vector<MttkrpVariant>& mttkrp_f64_variants();
+// The narrow vector-ALU variant (mttkrp_narrow.hip), listed after the
+// matrix-core float64 variants: one 16-column tile (ldc == 16), mode 0 of at most 256
+// rows (at most 128 with more than 8 columns), K chunks of whole mode-0
+// fibers for the other modes.
+constexpr int kNarrowInstr = 32;
+bool narrow_supports(int I0, int ncols);
+const MttkrpVariant& mttkrp_narrow_variant();
 const std::vector<MttkrpVariant>& mttkrp_split_variants();    // two bf16 terms
 const std::vector<MttkrpVariant>& mttkrp_split3_variants();   // three bf16 terms
 
