@@ -173,9 +173,9 @@ int split_cap(int64_t rows, int64_t ldc, int64_t J) {
   const int64_t budget = std::max<int64_t>(128ll << 20, 4 * plane);
   int64_t s = budget / std::max<int64_t>(plane, 1);
   // (16-column problems: small planes, and the narrow variant needs more
-  // chunks to fill the chip)
+  // chunks to fill the chip, each of at least 16 fibers)
   s = std::min<int64_t>(s, ldc <= 16 ? 512 : 128);
-  s = std::min<int64_t>(s, std::max<int64_t>(1, J / 64));
+  s = std::min<int64_t>(s, std::max<int64_t>(1, J / (ldc <= 16 ? 16 : 64)));
   return (int)std::max<int64_t>(s, 1);
 }
 
@@ -314,7 +314,16 @@ struct ModeShape {
   bool buf_ok;   // tensor and factors addressable with 32-bit byte offsets
   int64_t i0 = 0;       // size of mode 0 (the fibers the narrow variant walks)
   bool mode0 = false;   // the output mode is mode 0 (rows contiguous)
+  int order = 0;        // N
 };
+
+// The narrow variant's fibers (all of them for mode 0, one output row's
+// otherwise) and the fewest K chunks that hold them.
+int64_t narrow_fibers(const ModeShape& s) { return s.mode0 ? s.J : s.J / std::max<int64_t>(s.i0, 1); }
+int64_t narrow_min_splits(const ModeShape& s) {
+  const int64_t cap = narrow_max_chunk_fibers((int)s.i0, s.ncols, s.mode0, s.order);
+  return (narrow_fibers(s) + cap - 1) / cap;
+}
 
 // Float64 kernels with buffer loads (instr bit 16) address the tensor and
 // the factors with 32-bit byte offsets: usable when each is below 2^31
@@ -323,7 +332,7 @@ constexpr int64_t kBufLimit = (int64_t(1) << 31) - (int64_t(1) << 24);
 bool usable(const MttkrpVariant& x, const ModeShape& s) {
   if (x.instr & kNarrowInstr)
     return s.ldc == 16 && s.i0 > 0 && narrow_supports((int)std::min<int64_t>(s.i0, 1 << 20), s.ncols) &&
-           (s.mode0 ? s.M == s.i0 : true);
+           (s.mode0 ? s.M == s.i0 : true) && narrow_min_splits(s) <= s.split_max;
   return !(x.instr & 16) || s.buf_ok;
 }
 
@@ -338,11 +347,12 @@ Tiling make_tiling(const std::vector<MttkrpVariant>& vars, int v, const ModeShap
 
 int default_splits(const Tiling& t, const ModeShape& s) {
   if (t.instr & kNarrowInstr) {
-    // about two blocks per compute unit, at least 16 fibers per chunk
-    const int64_t rt = s.mode0 ? 1 : (s.M + 3) / 4;
-    const int64_t fibers = s.mode0 ? s.J : s.J / std::max<int64_t>(s.i0, 1);
-    int64_t sp = (2 * kNumCU + rt - 1) / rt;
-    sp = std::min<int64_t>(sp, std::max<int64_t>(1, fibers / 16));
+    // the largest chunks (the fewest partials; a mode > 0 row in one block
+    // where it fits, then no partials at all), unless the rows are too few
+    // to give half the compute units a block
+    int64_t sp = narrow_min_splits(s);
+    if (!s.mode0 && 2 * s.M < kNumCU)
+      sp = std::max(sp, std::min(narrow_fibers(s), (kNumCU + s.M - 1) / s.M));
     return (int)std::max<int64_t>(1, std::min<int64_t>(sp, s.split_max));
   }
   const int64_t tiles = ((s.M + t.bm() - 1) / t.bm()) * ((s.ncols + t.bn() - 1) / t.bn());
@@ -408,6 +418,7 @@ ModeShape mode_shape(const jkc_ctx* ctx, int n, int split_max) {
   s.buf_ok = ok;
   s.i0 = ctx->nterm > 0 ? 0 : ctx->dims[0];   // float64 path only
   s.mode0 = n == 0;
+  s.order = ctx->N;
   return s;
 }
 
@@ -542,10 +553,6 @@ const std::vector<MttkrpVariant>& variants_for(const jkc_ctx* ctx) {
 jkc_status launch_mttkrp_timed(jkc_ctx* ctx, const MttkrpArgs& a, const Tiling& t, int slot,
                                bool reduce_follows);
 
-// Enqueue the fused MTTKRP of mode n.  Result: split-K partials in
-// ctx->partial (t.splits > 1) or the product itself in ctx->Mbuf.  When
-// reduce_follows, the reduction launched next (launch_reduce_timed) closes
-// the launch's timing window.
 // K chunking of mode n's MTTKRP under tiling t: K elements per split and
 // the number of splits (split paths: whole wraps of the low mode).
 void chunking(const jkc_ctx* ctx, int n, const Tiling& t, int64_t* kchunk, int* splits) {
@@ -553,10 +560,20 @@ void chunking(const jkc_ctx* ctx, int n, const Tiling& t, int64_t* kchunk, int* 
   if (ctx->nterm > 0) {
     J = ctx->P / (ctx->dims[n] * ctx->dims[ctx->tp_low[n]]);   // wraps
     step = 1;
+  } else if (t.instr & kNarrowInstr) {
+    // the narrow variant: chunks of whole mode-0 fibers (of one output row
+    // for n > 0), at most what one block takes
+    const int64_t I0 = ctx->dims[0];
+    const int64_t fib = n == 0 ? ctx->P / I0 : ctx->P / (I0 * ctx->dims[n]);
+    const int64_t cap =
+        narrow_max_chunk_fibers((int)std::min<int64_t>(I0, 1 << 20), ctx->C_act, n == 0, ctx->N);
+    const int64_t kcf = std::min<int64_t>(std::max<int64_t>(1, (fib + t.splits - 1) / t.splits), cap);
+    *kchunk = n == 0 ? kcf : kcf * I0;
+    *splits = (int)((fib + kcf - 1) / kcf);
+    return;
   } else {
     J = ctx->P / ctx->dims[n];
-    // the narrow variant's chunks are whole mode-0 fibers
-    step = ((t.instr & kNarrowInstr) && n != 0) ? ctx->dims[0] : t.bk;
+    step = t.bk;
   }
   int64_t kc = align_up((J + t.splits - 1) / t.splits, step);
   *kchunk = kc;
@@ -564,10 +581,20 @@ void chunking(const jkc_ctx* ctx, int n, const Tiling& t, int64_t* kchunk, int* 
 }
 
 // Enqueue the fused MTTKRP of mode n.  Result: split-K partials in
-// ctx->partial (t.splits > 1) or the product itself in ctx->Mbuf.  When
+// ctx->partial (t.splits > 1) or the product itself in ctx->Mbuf; with fin
+// (the narrow tiling only), the reduced product in fin->out instead.  When
 // reduce_follows, the reduction launched next (launch_reduce_timed) closes
 // the launch's timing window.
-jkc_status enqueue_mttkrp(jkc_ctx* ctx, int n, const Tiling& t, bool reduce_follows = false) {
+// Reduced output of an MTTKRP whose kernels sum their own split-K partials
+// (the narrow tiling): out (ld ldo, ncols columns), Case I rows cleared when
+// zero_rows.
+struct FinOut {
+  double* out;
+  int32_t ldo, ncols, zero_rows;
+};
+
+jkc_status enqueue_mttkrp(jkc_ctx* ctx, int n, const Tiling& t, bool reduce_follows = false,
+                          const FinOut* fin = nullptr) {
   const auto& vars = variants_for(ctx);
   if (t.variant < 0 || t.variant >= (int)vars.size()) return fail(JKC_ESTATE, "no tiling");
   MttkrpArgs a{};
@@ -634,6 +661,14 @@ jkc_status enqueue_mttkrp(jkc_ctx* ctx, int n, const Tiling& t, bool reduce_foll
   } else {
     a.partial = ctx->Mbuf;
   }
+  if (fin) {
+    if (!(t.instr & kNarrowInstr)) return fail(JKC_ESTATE, "tiling has no split-K finish");
+    a.fin_out = fin->out;
+    a.fin_ldo = fin->ldo;
+    a.fin_ncols = fin->ncols;
+    a.fin_zero = fin->zero_rows;
+    a.fin_lo = ctx->left_out();
+  }
   return launch_mttkrp_timed(ctx, a, t, n, reduce_follows);
 }
 
@@ -692,17 +727,34 @@ int effective_splits(const jkc_ctx* ctx, int n, const Tiling& t) {
   return splits;
 }
 
-// MTTKRP of mode n reduced into out (ld ldo, ncols columns), with the Case I
-// row removal when n is the sampled mode.
-jkc_status enqueue_mttkrp_reduced(jkc_ctx* ctx, int n, double* out, int ldo, int ncols) {
-  const Tiling& t = ctx->tiling[n];
+// Whether the reduced MTTKRP of mode n under tiling t into out has the Case
+// I rows cleared: always, except for an unsplit product left in Mbuf by a
+// kernel without its own finish (the consumer clears them).
+bool reduced_clears_rows(const jkc_ctx* ctx, int n, const Tiling& t, const double* out) {
+  if (t.instr & kNarrowInstr) return true;
+  return !(effective_splits(ctx, n, t) == 1 && out == ctx->Mbuf);
+}
+
+// MTTKRP of mode n under tiling t reduced into out (ld ldo, ncols columns),
+// with the Case I row removal when n is the sampled mode (see
+// reduced_clears_rows for the one exception).
+jkc_status enqueue_mttkrp_reduced(jkc_ctx* ctx, int n, const Tiling& t, double* out, int ldo,
+                                  int ncols) {
+  const int zero = n == ctx->nhat ? 1 : 0;
+  if (t.instr & kNarrowInstr) {   // the kernels sum their own partials
+    const FinOut fin{out, ldo, ncols, zero};
+    return enqueue_mttkrp(ctx, n, t, false, &fin);
+  }
   const int splits = effective_splits(ctx, n, t);
-  const bool reduce = !(splits == 1 && out == ctx->Mbuf);   // else rows cleared by the consumer
+  const bool reduce = reduced_clears_rows(ctx, n, t, out);
   JKC_TRY(enqueue_mttkrp(ctx, n, t, reduce));
   if (!reduce) return JKC_OK;
   const double* src = splits > 1 ? ctx->partial : ctx->Mbuf;
-  return launch_reduce_timed(ctx, src, splits, (int32_t)ctx->dims[n], ncols, n == ctx->nhat ? 1 : 0,
-                             out, ldo);
+  return launch_reduce_timed(ctx, src, splits, (int32_t)ctx->dims[n], ncols, zero, out, ldo);
+}
+
+jkc_status enqueue_mttkrp_reduced(jkc_ctx* ctx, int n, double* out, int ldo, int ncols) {
+  return enqueue_mttkrp_reduced(ctx, n, ctx->tiling[n], out, ldo, ncols);
 }
 
 // W = T x_2 U_2 over the active columns (tree.hip explains the scheme):
@@ -789,7 +841,7 @@ jkc_status enqueue_update(jkc_ctx* ctx, int n, double tol, int check_conv) {
     // itself, each element is read and then overwritten by the same block)
     a.Utmp = ctx->Mbuf;
     a.nch = (int32_t)((ctx->maxI + kUpdRows - 1) / kUpdRows);
-  } else if (staged && splits <= kFuseMaxSplits) {
+  } else if (staged && splits <= kFuseMaxSplits && !(ctx->tiling[n].instr & kNarrowInstr)) {
     // few partials: the update sums them itself while staging M in LDS
     JKC_TRY(enqueue_mttkrp(ctx, n, ctx->tiling[n]));
     a.partial = splits > 1 ? ctx->partial : ctx->Mbuf;
@@ -982,7 +1034,7 @@ jkc_status enqueue_loss_grad(jkc_ctx* ctx, double* loss) {
       JKC_TRY(enqueue_tree_pass(ctx, n));
     else
       JKC_TRY(enqueue_mttkrp_reduced(ctx, n, ctx->Mbuf, ctx->ldc, ctx->ldc));
-    if ((from_w || effective_splits(ctx, n, ctx->tiling[n]) == 1) && n == ctx->nhat) {
+    if ((from_w || !reduced_clears_rows(ctx, n, ctx->tiling[n], ctx->Mbuf)) && n == ctx->nhat) {
       // the direct product still carries row p: clear it through a reduce pass
       JKC_HIP(launch_reduce(ctx->Mbuf, 1, (int32_t)ctx->dims[n], ctx->ldc, ctx->ldc, ctx->left_out(),
                             1, ctx->Mbuf, ctx->ldc, ctx->stream, nullptr));
@@ -1273,12 +1325,7 @@ jkc_status jk_cals_mttkrp(jkc_ctx* ctx, int32_t mode, double* out) {
   JKC_TRY(check_ctx(ctx));
   JKC_TRY(check_mode(ctx, mode));
   if (!out) return fail(JKC_EINVAL, "out is NULL");
-  const Tiling& t = ctx->tiling[mode];
-  JKC_TRY(enqueue_mttkrp(ctx, mode, t, true));
-  const int splits = effective_splits(ctx, mode, t);
-  JKC_TRY(launch_reduce_timed(ctx, splits > 1 ? ctx->partial : ctx->Mbuf, splits,
-                              (int32_t)ctx->dims[mode], ctx->C, mode == ctx->nhat ? 1 : 0, out,
-                              ctx->C));
+  JKC_TRY(enqueue_mttkrp_reduced(ctx, mode, out, ctx->C, ctx->C));
   g_last_error.clear();
   return JKC_OK;
 }
@@ -1666,7 +1713,6 @@ jkc_status jk_cals_tune(jkc_ctx* ctx, int32_t reps) {
         if (ci == 2 && cands[2] == cands[1]) continue;
         Tiling t = base;
         t.splits = cands[ci];
-        const int eff = is_tree ? 1 : effective_splits(ctx, n, t);
         // warm-up, then timed repetitions of MTTKRP + reduction
         auto run = [&]() -> jkc_status {
           if (is_tree) {
@@ -1676,12 +1722,7 @@ jkc_status jk_cals_tune(jkc_ctx* ctx, int32_t reps) {
             ctx->tree_tiling = keep;
             return r;
           }
-          JKC_TRY(enqueue_mttkrp(ctx, n, t));
-          if (eff > 1)
-            JKC_HIP(launch_reduce(ctx->partial, eff, (int32_t)ctx->dims[n], ctx->ldc, ctx->ldc,
-                                  ctx->left_out(), n == ctx->nhat ? 1 : 0, ctx->Mbuf, ctx->ldc,
-                                  ctx->stream, nullptr));
-          return JKC_OK;
+          return enqueue_mttkrp_reduced(ctx, n, t, ctx->Mbuf, ctx->ldc, ctx->ldc);
         };
         result = run();
         if (result != JKC_OK) break;

@@ -33,10 +33,18 @@ struct Tiling {
   int variant = -1;   // index into the kernel table (precision specific)
   int wm = 0, wn = 0, tm = 0, tn = 0, bk = 0, instr = 0;
   int splits = 1;
-  // rows per block (the narrow variant: 4 output rows, one per wavefront,
-  // for modes other than 0)
-  int bm() const { return (instr & 32) ? 4 : wm * tm * ((instr & 7) == 2 ? 4 : 16); }
+  // rows per block (the narrow variant: one output row for modes other
+  // than 0)
+  int bm() const { return (instr & 32) ? 1 : wm * tm * ((instr & 7) == 2 ? 4 : 16); }
   int bn() const { return wn * tn * 16; }
+};
+
+// Left-out rows of the sampled mode: column c belongs to model colmodel[c]
+// (-1: padding), and row i is left out of model k when lomask[i * K + k].
+struct LeftOut {
+  const int32_t* colmodel;
+  const uint8_t* lomask;
+  int32_t K;
 };
 
 struct MttkrpArgs {
@@ -67,6 +75,16 @@ struct MttkrpArgs {
   int32_t mtiles, ntiles;
   int32_t splits;
   double* partial;          // [splits][M][ldc]
+  // Reduced output (kernels that sum their own split-K partials; null: the
+  // partials are left for a separate reduction): out[i * fin_ldo + c] for
+  // c < fin_ncols (columns at or past ncols are 0), rows left out of column
+  // c's model 0 when fin_zero.
+  double* fin_out;
+  int32_t fin_ldo, fin_ncols, fin_zero;
+  LeftOut fin_lo;
+  // Narrow variant (set by its launcher): fibers of an output row (all
+  // fibers for mode 0) and per K chunk.
+  int32_t nfib, kcf;
 };
 
 // Kernel table entries (defined in the .hip files).
@@ -81,9 +99,12 @@ const std::vector<MttkrpVariant>& mttkrp_f64_variants();
 // The narrow vector-ALU variant (mttkrp_narrow.hip), listed after the
 // matrix-core float64 variants: one 16-column tile (ldc == 16), mode 0 of at most 256
 // rows (at most 128 with more than 8 columns), K chunks of whole mode-0
-// fibers for the other modes.
+// fibers for the other modes.  With fin_out set it produces the reduced
+// product itself.  A K chunk holds at most narrow_max_chunk_fibers fibers
+// (all fibers for mode 0, those of one output row otherwise).
 constexpr int kNarrowInstr = 32;
 bool narrow_supports(int I0, int ncols);
+int64_t narrow_max_chunk_fibers(int I0, int ncols, bool mode0, int order);
 const MttkrpVariant& mttkrp_narrow_variant();
 const std::vector<MttkrpVariant>& mttkrp_split_variants();    // two bf16 terms
 const std::vector<MttkrpVariant>& mttkrp_split3_variants();   // three bf16 terms
@@ -174,11 +195,6 @@ hipError_t launch_gram(const GramArgs& a, hipStream_t s);
 // Left-out rows of the sampled mode, as the kernels that clear them see
 // them: the owning model of every column ([ldc], -1 for padding) and the
 // row mask of the model table.
-struct LeftOut {
-  const int32_t* colmodel;
-  const uint8_t* lomask;
-  int32_t K;
-};
 hipError_t launch_tree_pass(const double* W, const double* F, int32_t S, int64_t ostep,
                             int64_t sstep, int32_t nout, int32_t ldc, int32_t ncols, double* out,
                             hipStream_t s);

@@ -57,6 +57,25 @@ def test_narrow_mttkrp_matches_oracle_every_mode(spec):
                 assert max(fro, mx) <= TOL, (splits, n, k, fro, mx)
 
 
+def test_narrow_finish_repeats_bitwise():
+    """The kernels' own split-K finish leaves its arrival counters zeroed:
+    repeated launches give the same bits, with ragged row tiles (31 and 22
+    rows) and chunk counts that do not divide the fibers."""
+    wl = synth.random_problem(111, (45, 31, 22), [4, 3], [7, -1], noise=0.1)
+    say("narrow finish repeats")
+    ctx = make_ctx(wl)
+    v = _narrow_index(ctx)
+    for splits in (5, 17):
+        for n in range(3):
+            ctx.set_tiling(n, v, splits)
+            first = to_np(ctx.mttkrp(n))
+            for _ in range(3):
+                assert np.array_equal(to_np(ctx.mttkrp(n)), first), (splits, n)
+            for k in range(wl.K):
+                fro, mx = errors(first[:, cols(wl, k)], oracle_model_mttkrp(wl, k, n))
+                assert max(fro, mx) <= TOL, (splits, n, k, fro, mx)
+
+
 def test_narrow_float32_delete_d_and_agreement_with_matrix_cores():
     wl = synth.random_problem(108, (33, 20, 19), [3, 4, 2], [[-1, -1], [0, 32], [5, 6]], noise=0.1,
                               dtype=np.float32)
