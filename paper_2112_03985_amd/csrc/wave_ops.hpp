@@ -30,8 +30,11 @@ __device__ inline double lane_f64(double v, int lane) {
 // partial sums in either order, and a + b == b + a exactly, so every lane of
 // a row holds the same bits), then the four row sums in the fixed order
 // (r0 + r1) + (r2 + r3).  Every lane gets the result; the same lanes combine
-// in the same order on every run.
+// in the same order on every run.  The additions are not contracted: were
+// the caller's last product fused into the first one, the two lanes of a
+// pair would round differently and the sum would depend on the call site.
 __device__ inline double wave_sum(double v) {
+#pragma clang fp contract(off)
   v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
   v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
   v += dpp_f64<0x141>(v);   // row_half_mirror: the other quad of the eight
