@@ -23,7 +23,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libjkcals.so")
+# JKCALS_LIBRARY names another build of the library (the host-sanitizer build
+# of the validation and planning code, libjkcals_asan.so); default in-tree
+LIB_PATH = os.environ.get("JKCALS_LIBRARY") or os.path.join(_HERE, "libjkcals.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "jk_cals.h")
 
 JKC_OK, JKC_EINVAL, JKC_ENOMEM, JKC_EDEVICE, JKC_ESTATE, JKC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
