@@ -464,25 +464,78 @@ __global__ void __launch_bounds__(kUpdThreads) k_update_lds(const UpdateArgs a) 
     const bool zero = a.n == a.nhat;
     const int RR = R * R;
 
-    // The Gram factors of H, loaded in the first round of M's loads, after
-    // them, and multiplied once M is stored (1.0 stands in for the skipped
-    // modes; x * 1.0 == x exactly, so the product keeps the ascending-mode
-    // order and bits of the oracle's).
+    // The Gram factors of H, loaded before M's first round (every mode's
+    // plane is read, a present one standing in for the skipped modes, so no
+    // load sits behind a branch; 1.0 replaces the skipped modes' values, and
+    // x * 1.0 == x exactly, so the product keeps the ascending-mode order and
+    // bits of the oracle's).  For R <= 8 wavefront 0 forms H, factors it and
+    // forms H^{-1} as soon as these arrive, while the other wavefronts load
+    // and stage M; larger ranks factor after M is stored.
     constexpr int kHPer = (kMaxRank * kMaxRank + kUpdThreads - 1) / kUpdThreads;
+    const bool early = R <= 8;
     double hg[kHPer][kMaxOrder];
-    // M: kStage elements per thread per round, their loads (and the left-out
-    // row flags) issued before any of them is stored (one memory latency per
-    // round); partials summed in ascending split order
     {
+      const int present = a.n == 0 ? 1 : 0;
+#pragma unroll
+      for (int u = 0; u < kHPer; ++u) {
+        const int e = t + u * kUpdThreads;
+        const int64_t ge = goff + (e < RR ? e : 0);
+#pragma unroll
+        for (int mm = 0; mm < kMaxOrder; ++mm) {
+          const bool use = mm < a.N && mm != a.n;
+          const double g = a.G[use ? mm : present][ge];
+          hg[u][mm] = use ? g : 1.0;
+        }
+      }
+    }
+    auto form_h = [&]() __attribute__((always_inline)) {
+#pragma unroll
+      for (int u = 0; u < kHPer; ++u) {
+        const int e = t + u * kUpdThreads;
+        if (e < RR) {
+          double h = hg[u][0];
+#pragma unroll
+          for (int m = 1; m < kMaxOrder; ++m) h *= hg[u][m];
+          H[(e / R) * ld + e % R] = h;
+        }
+      }
+    };
+    if (early && t < 64) {
+      // wavefront 0 (R^2 <= 64 entries): H, its Cholesky factor and L^{-1}
+      // in registers (chol_inv_regs), then H^{-1} = L^{-T} L^{-1} with the
+      // upper triangle mirrored, ordered by wavefront-local syncs; the
+      // other wavefronts load and stage M meanwhile
+      form_h();
+      wave_lds_sync();
+      const bool all_ok = chol_inv_regs<8>(H, X, ld, R, t);
+      if (t == 0) s_flag = all_ok ? 1 : 0;
+      wave_lds_sync();
+      if (all_ok && t < RR) {
+        const int r = t / R, c = t % R;
+        if (r <= c) {
+          double acc = 0.0;
+          for (int q = c; q < R; ++q) acc += X[q * ld + r] * X[q * ld + c];
+          L[r * ld + c] = acc;
+          L[c * ld + r] = acc;
+        }
+      }
+    }
+    // M: kStage elements per thread per round (by the wavefronts other than
+    // 0 when wavefront 0 factors H meanwhile), their loads (and the
+    // left-out row flags) issued before any of them is stored (one memory
+    // latency per round); partials summed in ascending split order
+    const int tw = early ? t - 64 : t;
+    const int nw = early ? kUpdThreads - 64 : kUpdThreads;
+    if (tw >= 0) {
       constexpr int kStage = 4;
       const int nel = a.In * R;
-      for (int e0 = 0; e0 == 0 || e0 < nel; e0 += kStage * kUpdThreads) {
+      for (int e0 = 0; e0 == 0 || e0 < nel; e0 += kStage * nw) {
         double m[kStage];
         bool lo[kStage];
         if (a.splits == 1 && nel > 0) {
 #pragma unroll
           for (int u = 0; u < kStage; ++u) {
-            const int e = e0 + u * kUpdThreads + t;
+            const int e = e0 + u * nw + tw;
             const int ec = e < nel ? e : 0;
             const int i = ec / R, r = ec - (ec / R) * R;
             m[u] = a.partial[(int64_t)i * a.ldc + off + r];
@@ -494,7 +547,7 @@ __global__ void __launch_bounds__(kUpdThreads) k_update_lds(const UpdateArgs a) 
         } else {
 #pragma unroll
           for (int u = 0; u < kStage; ++u) {
-            const int e = e0 + u * kUpdThreads + t;
+            const int e = e0 + u * nw + tw;
             m[u] = 0.0;
             lo[u] = false;
             if (e < nel) {
@@ -505,19 +558,9 @@ __global__ void __launch_bounds__(kUpdThreads) k_update_lds(const UpdateArgs a) 
             }
           }
         }
-        if (e0 == 0) {
-#pragma unroll
-          for (int u = 0; u < kHPer; ++u) {
-            const int e = t + u * kUpdThreads;
-            const int64_t ge = goff + (e < RR ? e : 0);
-#pragma unroll
-            for (int mm = 0; mm < kMaxOrder; ++mm)
-              hg[u][mm] = (mm < a.N && mm != a.n) ? a.G[mm][ge] : 1.0;
-          }
-        }
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
-          const int e = e0 + u * kUpdThreads + t;
+          const int e = e0 + u * nw + tw;
           if (e < nel) {
             const int i = e / R, r = e - (e / R) * R;
             Ms[i * ld + r] = lo[u] ? 0.0 : m[u];
@@ -525,28 +568,14 @@ __global__ void __launch_bounds__(kUpdThreads) k_update_lds(const UpdateArgs a) 
         }
       }
     }
-#pragma unroll
-    for (int u = 0; u < kHPer; ++u) {
-      const int e = t + u * kUpdThreads;
-      if (e < RR) {
-        double h = hg[u][0];
-#pragma unroll
-        for (int m = 1; m < kMaxOrder; ++m) h *= hg[u][m];
-        H[(e / R) * ld + e % R] = h;
-      }
-    }
+    if (!early) form_h();
     __syncthreads();
 
-    // Cholesky and L^{-1} in wavefront 0: in registers for R <= 8
-    // (chol_inv_regs), else in LDS with its steps ordered by wavefront-local
-    // syncs: pivots by lane 0, the column below by lanes i > j; then, if
-    // every pivot passed, lane j forms column j of L^{-1}
-    if (R <= 8) {
-      if (t < 64) {
-        const bool all_ok = chol_inv_regs<8>(H, X, ld, R, t);
-        if (t == 0) s_flag = all_ok ? 1 : 0;
-      }
-    } else if (t < 64) {
+    // R > 8: Cholesky and L^{-1} in wavefront 0, in LDS with its steps
+    // ordered by wavefront-local syncs: pivots by lane 0, the column below
+    // by lanes i > j; then, if every pivot passed, lane j forms column j of
+    // L^{-1}
+    if (!early && t < 64) {
       double maxdiag = 0.0;
       for (int j = 0; j < R; ++j) maxdiag = fmax(maxdiag, H[j * ld + j]);
       const double thresh = kPivotTolPerRank * R * maxdiag;
@@ -582,16 +611,18 @@ __global__ void __launch_bounds__(kUpdThreads) k_update_lds(const UpdateArgs a) 
     const bool chol_ok = s_flag != 0;
 
     if (chol_ok) {
-      for (int e = t; e < R * R; e += blockDim.x) {
-        const int r = e / R, c = e % R;
-        if (r <= c) {
-          double acc = 0.0;
-          for (int q = c; q < R; ++q) acc += X[q * ld + r] * X[q * ld + c];
-          L[r * ld + c] = acc;
-          L[c * ld + r] = acc;
+      if (!early) {   // (R <= 8: H^{-1} formed by wavefront 0 above)
+        for (int e = t; e < R * R; e += blockDim.x) {
+          const int r = e / R, c = e % R;
+          if (r <= c) {
+            double acc = 0.0;
+            for (int q = c; q < R; ++q) acc += X[q * ld + r] * X[q * ld + c];
+            L[r * ld + c] = acc;
+            L[c * ld + r] = acc;
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();
     } else {
       for (int e = t; e < R * R; e += blockDim.x) {
         const int r = e / R, c = e % R;
