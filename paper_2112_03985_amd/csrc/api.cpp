@@ -348,10 +348,11 @@ Tiling make_tiling(const std::vector<MttkrpVariant>& vars, int v, const ModeShap
 int default_splits(const Tiling& t, const ModeShape& s) {
   if (t.instr & kNarrowInstr) {
     // the largest chunks (the fewest partials; a mode > 0 row in one block
-    // where it fits, then no partials at all), unless the rows are too few
-    // to give half the compute units a block
+    // where it fits), with at least one block per compute unit for modes
+    // n > 0 (two chunks per row on the 200-row modes of the benchmark: the
+    // update sums two partials itself, so no reduction pass follows)
     int64_t sp = narrow_min_splits(s);
-    if (!s.mode0 && 2 * s.M < kNumCU)
+    if (!s.mode0 && s.M < kNumCU)
       sp = std::max(sp, std::min(narrow_fibers(s), (kNumCU + s.M - 1) / s.M));
     return (int)std::max<int64_t>(1, std::min<int64_t>(sp, s.split_max));
   }
@@ -841,7 +842,7 @@ jkc_status enqueue_update(jkc_ctx* ctx, int n, double tol, int check_conv) {
     // itself, each element is read and then overwritten by the same block)
     a.Utmp = ctx->Mbuf;
     a.nch = (int32_t)((ctx->maxI + kUpdRows - 1) / kUpdRows);
-  } else if (staged && splits <= kFuseMaxSplits && !(ctx->tiling[n].instr & kNarrowInstr)) {
+  } else if (staged && splits <= kFuseMaxSplits) {
     // few partials: the update sums them itself while staging M in LDS
     JKC_TRY(enqueue_mttkrp(ctx, n, ctx->tiling[n]));
     a.partial = splits > 1 ? ctx->partial : ctx->Mbuf;
