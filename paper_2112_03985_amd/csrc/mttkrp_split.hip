@@ -63,13 +63,15 @@ constexpr int kFlushSteps = 64;   // float32 accumulation span within a long wra
 constexpr int kXcds = 8;
 
 // LDS rows of 32 bf16 (four 16-byte chunks) with the chunk index XOR-ed by
-// g(row) = ((row >> 1) mod 4) ^ ((row >> 3) mod 2): the fragment reads (lanes of a
-// 16-lane group on 16 consecutive rows, one chunk) and the staging writes
-// (4 consecutive lanes per row, all four chunks) then hit distinct banks,
-// both for 64 four-byte banks served 16 lanes at a time and for 32 banks
-// served 8 lanes at a time (checked exhaustively on the host).
+// g(row) = ((row >> 2) ^ (row >> 1)) mod 4: the fragment reads (lane l: row
+// l mod 16 of a 16-row tile, chunk l / 16) and the staging writes (4
+// consecutive lanes per row, all four chunks) then hit distinct banks for
+// 16 and for 32 consecutive lanes (checked on the host), and the LDS
+// bank-conflict counter reads zero for both on gfx950, where the earlier
+// g(row) = ((row >> 1) mod 4) ^ ((row >> 3) mod 2), distinct only within
+// groups of 16 lanes, measured two-way conflicts on the fragment reads.
 // (g depends on row mod 16 only, so a fragment row's chunk follows from its lane.)
-__device__ __forceinline__ int swz(int row) { return ((row >> 1) & 3) ^ ((row >> 3) & 1); }
+__device__ __forceinline__ int swz(int row) { return ((row >> 2) ^ (row >> 1)) & 3; }
 
 // BRES: the block's B operand (its columns of U_L, all ilp rows) is loaded
 // into dynamic LDS once and stays there (U_L is the same for every wrap), so

@@ -1,14 +1,16 @@
 """Host-side checks of the split-precision kernel's LDS layout: rows of 32
 bfloat16 (four 16-byte chunks) whose chunk index is XOR-ed with
-g(row) = ((row >> 1) mod 4) ^ ((row >> 3) mod 2).  The matrix-core fragment
-reads (lane l: row l mod 16 of a 16-row tile, chunk l // 16) and the staging
-writes (thread e: row e // 4, chunk e mod 4) must fall on distinct banks in
-every group of lanes the LDS serves together, for 64 four-byte banks served
-16 lanes at a time and for 32 banks served 8 lanes at a time."""
+g(row) = ((row >> 2) ^ (row >> 1)) mod 4.  The matrix-core fragment reads
+(lane l: row l mod 16 of a 16-row tile, chunk l // 16) and the staging writes
+(thread e: row e // 4, chunk e mod 4) must fall on distinct 16-byte bank
+slots within 8, 16 and 32 consecutive lanes (the LDS bank-conflict counter
+reads zero for both patterns on gfx950 with this g; the earlier
+((row >> 1) mod 4) ^ ((row >> 3) mod 2), distinct within 16 lanes only,
+measured two-way conflicts on the fragment reads)."""
 
 
 def g(row):
-    return ((row >> 1) & 3) ^ ((row >> 3) & 1)
+    return ((row >> 2) ^ (row >> 1)) & 3
 
 
 def slot(row, chunk, nslots):
@@ -26,6 +28,7 @@ def test_fragment_reads_conflict_free():
         lanes = [(base + (l & 15), l >> 4) for l in range(64)]
         assert _distinct(lanes, 16, 16)
         assert _distinct(lanes, 8, 8)
+        assert _distinct(lanes, 32, 32)
 
 
 def test_staging_writes_conflict_free():
@@ -33,6 +36,7 @@ def test_staging_writes_conflict_free():
         lanes = [(e // 4, e % 4) for e in range(first, first + 64)]
         assert _distinct(lanes, 16, 16)
         assert _distinct(lanes, 8, 8)
+        assert _distinct(lanes, 32, 32)
 
 
 def test_unswizzled_layout_would_conflict():
