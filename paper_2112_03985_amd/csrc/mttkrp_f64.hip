@@ -118,11 +118,17 @@ k_mttkrp_f64(const MttkrpArgs a) {
   constexpr int RQ = NT / BK > 16 ? NT / BK : 16;
   constexpr int BMP = (BM + RQ - 1) / RQ * RQ;
   constexpr int BN = WN * TN * 16;
-  // Row pitches in LDS (doubles), chosen modulo 32 so that the fragment
-  // reads and the staging writes spread over the 64 four-byte banks: A rows
-  // at 20 (mod 32) for the row-strip reads (4 rows x 4 doubles) and the
-  // column-walk writes, 24 for 16-double row reads; B rows at 8.
-  constexpr int LDA = BMP + ((FAM == 2 ? 20 : 24) - BMP % 32 + 32) % 32;
+  // Row pitches in LDS (doubles).  Measured on gfx950: paired fragment reads
+  // (two doubles per lane) are free of bank conflicts at any pitch; a
+  // column-walk staging write (16 or 32 consecutive K rows of one column per
+  // wavefront, the layout of modes without unit stride) is free of them only
+  // at an odd pitch (4-way at 20 mod 32); a single strip read (4 doubles of
+  // each of 2 rows per half-wavefront) needs the pitch in [4, 28] mod 32; a
+  // single read of 16 doubles of each of 2 rows is 2-way at any pitch but 16
+  // (mod 32), which would make the column walk 16-way.  A rows therefore sit
+  // at 21 (mod 32) for every family; B rows, read in pairs and written along
+  // rows, at 8.
+  constexpr int LDA = BMP + (21 - BMP % 32 + 32) % 32;
   constexpr int LDB = BN + (8 - BN % 32 + 32) % 32;
   constexpr int VA = BMP * BK / NT;  // A elements per thread per step (one column)
   constexpr int VB = BN * BK / NT;   // B elements per thread per step (one column)
