@@ -319,7 +319,9 @@ jkc_status jk_cals_set_sweep_graph(jkc_ctx *ctx, int32_t enable);
 int32_t jk_cals_num_tilings(jkc_ctx *ctx);
 
 /* Force tiling `variant` (0 .. num_tilings-1) with `splits` K chunks
- * (clamped to 1 .. the context's limit) for `mode`.  Any tiling gives the
+ * (clamped to 1 .. the context's limit) for `mode`; mode = N selects the
+ * shared partial contraction W of 3-way float64 sweeps (splits must be 1;
+ * JKC_EINVAL when the context holds no W).  Any tiling gives the
  * same result up to the order of the float64 sums.  JKC_EINVAL for a
  * buffer-load tiling (its description ends in "-buffer") when the tensor or
  * a multi-factor takes 2^31 bytes or more, and for the narrow vector-ALU

@@ -1302,8 +1302,8 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
     const ModeShape shape = tree_shape(&c);
     if (!tune_lookup(&c, kTreeSlot, vars, shape, &c.tree_tiling)) {
       // untuned: the 16x16x4 tiling of 112 x 128 with four wavefronts, the
-      // tuner's choice on both measured shapes (100x200x200 at C = 500 and
-      // 300x250x200 at C = 82,500), else the cost model
+      // tuner's choice on 300x250x200 at C = 82,500 (on 100x200x200 at
+      // C = 500 the tuner prefers 80 x 128 by about 3 %), else the cost model
       c.tree_tiling = choose_tiling(vars, shape);
       for (int v = 0; v < (int)vars.size(); ++v) {
         const auto& x = vars[v];
@@ -1824,18 +1824,27 @@ int32_t jk_cals_num_tilings(jkc_ctx* ctx) {
 
 jkc_status jk_cals_set_tiling(jkc_ctx* ctx, int32_t mode, int32_t variant, int32_t splits) {
   JKC_TRY(check_ctx(ctx));
-  JKC_TRY(check_mode(ctx, mode));
+  const bool is_tree = ctx && mode == ctx->N;
+  if (!is_tree) JKC_TRY(check_mode(ctx, mode));
+  if (is_tree && !ctx->tree_avail)
+    return fail(JKC_EINVAL, "this context holds no shared partial contraction");
   const auto& vars = variants_for(ctx);
   if (variant < 0 || variant >= (int)vars.size()) return fail(JKC_EINVAL, "variant out of range");
   if (splits < 1) return fail(JKC_EINVAL, "splits must be >= 1");
-  const ModeShape shape = mode_shape(ctx, mode, ctx->split_max[mode]);
+  if (is_tree && splits != 1)
+    return fail(JKC_EINVAL, "the shared partial contraction takes one K chunk (splits = 1)");
+  const ModeShape shape = is_tree ? tree_shape(ctx) : mode_shape(ctx, mode, ctx->split_max[mode]);
   if (!usable(vars[variant], shape))
     return fail(JKC_EINVAL, (vars[variant].instr & kNarrowInstr)
                                 ? "the narrow tiling needs at most 16 columns (ldc 16) and mode 0 of "
                                   "at most 256 rows (128 with more than 8 columns), float64 path"
                                 : "this tiling needs the tensor and every factor below 2^31 bytes");
-  ctx->tiling[mode] = make_tiling(vars, variant, shape, splits);
-  ctx->describe[mode] = describe_tiling(ctx->tiling[mode], ctx->precision);
+  if (is_tree) {
+    ctx->tree_tiling = make_tiling(vars, variant, shape, 1);
+  } else {
+    ctx->tiling[mode] = make_tiling(vars, variant, shape, splits);
+    ctx->describe[mode] = describe_tiling(ctx->tiling[mode], ctx->precision);
+  }
   drop_graph(ctx);
   g_last_error.clear();
   return JKC_OK;

@@ -582,6 +582,7 @@ const std::vector<MttkrpVariant>& mttkrp_f64_variants() {
       JKC_F64_VARIANT(2, 4, 13, 4, 16, 26), // 104 x 256, 8 wavefronts
       JKC_F64_VARIANT(1, 4, 7, 2, 16, 24),  // 112 x 128, 16x16x4
       JKC_F64_VARIANT(2, 4, 4, 2, 16, 24),  // 128 x 128, 8 wavefronts, 16x16x4
+      JKC_F64_VARIANT(1, 4, 5, 2, 16, 24),  // 80 x 128, 16x16x4 (W on 20,000 rows: 1,000 blocks)
   };
   return v;
 }

@@ -77,3 +77,69 @@ def rel(a, b):
 
 def to_np(t):
     return t.detach().cpu().numpy()
+
+
+_FAMILY = {"mfma16x16x4": 0, "mfma4x4x4-diagonal": 1, "mfma4x4x4-strips": 2}
+
+
+def variant_geometry(desc):
+    """(wm, wn, tm, tn, bk, instr) of a float64 tiling description
+    ("f64 v34 wm1 wn4 tm7 tn2 bk16 s128 mfma16x16x4-interleaved-buffer"),
+    in the form of the tuned-tilings table; None for the narrow tiling."""
+    f = desc.split()
+    if f and f[0] == "tree":
+        f = f[1:]
+    suffix = f[8]
+    if suffix.startswith("valu-narrow"):
+        return None
+    instr = 0
+    if suffix.endswith("-buffer"):
+        instr += 16
+        suffix = suffix[: -len("-buffer")]
+    if suffix.endswith("-interleaved"):
+        instr += 8
+        suffix = suffix[: -len("-interleaved")]
+    instr += _FAMILY[suffix]
+    num = [int(x.lstrip("wmntbk")) for x in f[2:7]]
+    return tuple(num) + (instr,)
+
+
+def shipped_tilings(wl):
+    """Tilings of the shipped tuned table for this float64 workload: {slot:
+    ((wm, wn, tm, tn, bk, instr), splits)}, slot N the shared contraction."""
+    import os
+    C = int(sum(wl.ranks))
+    ldc = (C + 15) // 16 * 16
+    path = os.path.join(os.path.dirname(__file__), "..", "paper_2112_03985_amd", "tuned_gfx950.txt")
+    N = len(wl.dims)
+    key = "gfx950 p0 f32_%d N%d d%s ldc%d " % (int(wl.T.dtype == np.float32), N,
+                                              "x".join(str(d) for d in wl.dims), ldc)
+    out = {}
+    for line in open(path):
+        k, geo, sp = line.strip().split("|")
+        if not k.startswith(key):
+            continue
+        slot = k[len(key):]
+        n = N if slot == "tree" else int(slot[len("mode"):])
+        out[n] = (tuple(int(x) for x in geo.split()), int(sp))
+    return out
+
+
+def apply_tilings(ctx, tilings):
+    """Force the given {slot: (geometry, splits)} on ctx (slot N: the shared
+    contraction), finding each geometry's variant index from the
+    descriptions; returns the descriptions."""
+    import paper_2112_03985_amd as jk
+    N = ctx.N
+    index = {}
+    for v in range(ctx.num_tilings()):
+        try:
+            ctx.set_tiling(0, v, 1)
+        except jk.JkcError:
+            continue
+        g = variant_geometry(ctx.describe(0))
+        if g is not None:
+            index[g] = v
+    for n, (geo, splits) in sorted(tilings.items()):
+        ctx.set_tiling(n, index[geo], splits)
+    return [ctx.describe(n) for n in range(N + 1)]

@@ -8,7 +8,7 @@ import pytest
 import oracle
 import synth
 import paper_2112_03985_amd as jk
-from gpu_util import make_ctx, rel, say, to_np, cols
+from gpu_util import make_ctx, rel, say, to_np, cols, shipped_tilings, apply_tilings
 
 pytestmark = pytest.mark.gpu
 
@@ -81,6 +81,28 @@ def test_config2_sampled_models():
     res = oracle.jk_als(np.asarray(wl.T), 0, wl.ranks, wl.left_out, wl.init, 10,
                         models=models, record_factors=range(1, 11))
     ctx = make_ctx(wl)
+    for t in range(1, 11):
+        ctx.sweep(1)
+        _compare_iteration(wl, ctx, res, t, models=models)
+
+
+def test_config2_bench_tilings_sampled_models():
+    """The benchmark workload in the launch configuration bench.py times: the
+    tilings of the shipped tuned table (each mode's fused MTTKRP with its
+    split count, and the shared contraction W), sampled submodels checked per
+    iteration for 10 sweeps."""
+    wl = synth.config2()
+    models = [0, 50, 99]
+    ctx = make_ctx(wl)
+    tilings = shipped_tilings(wl)
+    assert sorted(tilings) == [0, 1, 2, 3]
+    descs = apply_tilings(ctx, tilings)
+    say("c2 bench tilings", descs)
+    for n in range(3):
+        assert (" s%d " % tilings[n][1]) in descs[n], descs[n]
+    assert descs[3].startswith("tree ")
+    res = oracle.jk_als(np.asarray(wl.T), 0, wl.ranks, wl.left_out, wl.init, 10,
+                        models=models, record_factors=range(1, 11))
     for t in range(1, 11):
         ctx.sweep(1)
         _compare_iteration(wl, ctx, res, t, models=models)

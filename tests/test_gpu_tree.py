@@ -10,7 +10,7 @@ import pytest
 import oracle
 import synth
 import paper_2112_03985_amd as jk
-from gpu_util import make_ctx, rel, say, to_np, cols
+from gpu_util import make_ctx, rel, say, to_np, cols, variant_geometry
 
 pytestmark = pytest.mark.gpu
 
@@ -153,3 +153,54 @@ def test_gradient_with_and_without_the_shared_contraction(spec):
     b.refine(5)
     for n in range(3):
         assert rel(to_np(a.get_factors(n)[0]), to_np(b.get_factors(n)[0])) <= 1e-11, n
+
+
+def test_tree_every_tiling_matches_oracle():
+    """Every compiled tiling computes W when forced on the shared-contraction
+    slot (mode N of jk_cals_set_tiling): one sweep matches the oracle's
+    per-submodel ALS at 1e-11, on a shape of several tiles with ragged tails
+    (W has 37 * 45 = 1665 rows, K = 23)."""
+    seed, dims, ranks, lo, nh = SPECS[0]
+    wl = synth.random_problem(seed, dims, ranks, lo, noise=0.1, sampled_mode=nh)
+    res = oracle.jk_als(np.asarray(wl.T), nh, wl.ranks, wl.left_out, wl.init, 1,
+                        record_factors=[1])
+    probe = make_ctx(wl)
+    checked = 0
+    for v in range(probe.num_tilings()):
+        ctx = make_ctx(wl)
+        try:
+            ctx.set_tiling(3, v, 1)
+        except jk.JkcError:
+            continue                      # the narrow tiling (at most 16 columns)
+        desc = ctx.describe(3)
+        assert desc.startswith("tree ") and (" v%d " % v) in desc, desc
+        say("tree tiling", desc)
+        ctx.sweep(1)
+        facs = [to_np(ctx.get_factors(n)[0]) for n in range(3)]
+        err = to_np(ctx.get_status()[0])
+        for k, r in res.items():
+            c = cols(wl, k)
+            ref = r.padded(r.U_hist[1])
+            for n in range(3):
+                assert rel(facs[n][:, c], ref[n]) <= 1e-11, (desc, k, n)
+            assert abs(err[k] - r.e_hist[0]) <= 1e-11 * r.normT2, (desc, k)
+        checked += 1
+    assert checked >= probe.num_tilings() - 1
+
+
+def test_tree_tiling_refusals():
+    wl = synth.random_problem(70, (12, 10, 9), [2, 3], [-1, 4])
+    ctx = make_ctx(wl)
+    v = 0                                 # a matrix-core tiling (not the narrow one)
+    ctx.set_tiling(0, v, 1)
+    assert variant_geometry(ctx.describe(0)) is not None
+    with pytest.raises(jk.JkcError):
+        ctx.set_tiling(3, v, 2)           # W takes one K chunk
+    with pytest.raises(jk.JkcError):
+        ctx.set_tiling(4, v, 1)           # past the shared-contraction slot
+    with pytest.raises(jk.JkcError):
+        ctx.set_tiling(3, ctx.num_tilings(), 1)
+    ctx.set_tiling(3, v, 1)
+    wl4 = synth.random_problem(71, (6, 5, 4, 3), [2, 2], [-1, 1])
+    with pytest.raises(jk.JkcError):
+        make_ctx(wl4).set_tiling(4, v, 1)  # no W for four-way tensors
