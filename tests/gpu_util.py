@@ -79,13 +79,15 @@ def to_np(t):
     return t.detach().cpu().numpy()
 
 
-_FAMILY = {"mfma16x16x4": 0, "mfma4x4x4-diagonal": 1, "mfma4x4x4-strips": 2}
+_FAMILY = {"mfma16x16x4": 0, "mfma4x4x4-diagonal": 1, "mfma4x4x4-strips": 2,
+           "mfma16x16x32bf16": 0}
 
 
 def variant_geometry(desc):
-    """(wm, wn, tm, tn, bk, instr) of a float64 tiling description
-    ("f64 v34 wm1 wn4 tm7 tn2 bk16 s128 mfma16x16x4-interleaved-buffer"),
-    in the form of the tuned-tilings table; None for the narrow tiling."""
+    """(wm, wn, tm, tn, bk, instr) of a tiling description
+    ("f64 v34 wm1 wn4 tm7 tn2 bk16 s128 mfma16x16x4-interleaved-buffer",
+    "bf16x3 v5 wm2 wn2 tm2 tn2 bk32 s8 mfma16x16x32bf16"), in the form of the
+    tuned-tilings table; None for the narrow tiling."""
     f = desc.split()
     if f and f[0] == "tree":
         f = f[1:]
@@ -104,16 +106,17 @@ def variant_geometry(desc):
     return tuple(num) + (instr,)
 
 
-def shipped_tilings(wl):
-    """Tilings of the shipped tuned table for this float64 workload: {slot:
-    ((wm, wn, tm, tn, bk, instr), splits)}, slot N the shared contraction."""
+def shipped_tilings(wl, precision=0):
+    """Tilings of the shipped tuned table (the ones bench.py times) for this
+    workload and precision (0 float64, 1 bf16x3, 2 bf16x6): {slot: ((wm, wn,
+    tm, tn, bk, instr), splits)}, slot N the shared contraction."""
     import os
     C = int(sum(wl.ranks))
     ldc = (C + 15) // 16 * 16
     path = os.path.join(os.path.dirname(__file__), "..", "paper_2112_03985_amd", "tuned_gfx950.txt")
     N = len(wl.dims)
-    key = "gfx950 p0 f32_%d N%d d%s ldc%d " % (int(wl.T.dtype == np.float32), N,
-                                              "x".join(str(d) for d in wl.dims), ldc)
+    key = "gfx950 p%d f32_%d N%d d%s ldc%d " % (precision, int(wl.T.dtype == np.float32), N,
+                                               "x".join(str(d) for d in wl.dims), ldc)
     out = {}
     for line in open(path):
         k, geo, sp = line.strip().split("|")
@@ -129,6 +132,7 @@ def apply_tilings(ctx, tilings):
     """Force the given {slot: (geometry, splits)} on ctx (slot N: the shared
     contraction), finding each geometry's variant index from the
     descriptions; returns the descriptions."""
+    assert tilings, "no tuned tilings for this workload"
     import paper_2112_03985_amd as jk
     N = ctx.N
     index = {}

@@ -2,13 +2,14 @@
 fixed-iteration protocol of Sec. 5.1), full-size workloads, sampled models
 (columns never interact, so a sample is valid while the GPU still runs the
 whole fused launch).  Every result's normwise and elementwise errors are
-printed; float64 gate 1e-11 per iteration where kappa(H) <= 1e4 (checked)."""
+printed; float64 gate 1e-11 per iteration where kappa(H) <= 1e4 (checked).
+Each context runs in the tilings bench.py times (the shipped tuned table)."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from gpu_util import errors, make_ctx, rel, say, to_np, cols
+from gpu_util import apply_tilings, errors, make_ctx, rel, say, shipped_tilings, to_np, cols
 
 pytestmark = pytest.mark.gpu
 
@@ -49,6 +50,7 @@ def test_config2_100_sweeps_sampled_models():
                         models=models, record_factors=range(1, sweeps + 1))
     say("c2 100-sweep trajectory: GPU")
     ctx = make_ctx(wl)
+    say("tilings", apply_tilings(ctx, shipped_tilings(wl)))
     worst = 0.0
     for t in range(1, sweeps + 1):
         ctx.sweep(1)
@@ -96,6 +98,7 @@ def test_config3_stratified_60_models_5_sweeps():
         assert np.linalg.cond(res[k].H_last) <= 1e4, k
     say("c3 stratified trajectory: GPU")
     ctx = make_ctx(wl)
+    say("tilings", apply_tilings(ctx, shipped_tilings(wl)))
     worst = 0.0
     for t in range(1, sweeps + 1):
         ctx.sweep(1)
@@ -119,6 +122,7 @@ def test_config5_20_sweeps_and_200_refinement_steps():
     res = oracle.jk_als(T, 0, wl.ranks, wl.left_out, wl.init, sweeps, models=models,
                         record_factors=range(1, sweeps + 1))
     ctx = make_ctx(wl)
+    say("tilings", apply_tilings(ctx, shipped_tilings(wl)))
     worst = 0.0
     for t in range(1, sweeps + 1):
         ctx.sweep(1)

@@ -19,7 +19,8 @@ import pytest
 import oracle
 import synth
 import paper_2112_03985_amd as jk
-from gpu_util import make_ctx, oracle_model_mttkrp, errors, rel, rel_fro, say, to_np, cols
+from gpu_util import (apply_tilings, make_ctx, oracle_model_mttkrp, errors, rel, rel_fro, say,
+                      shipped_tilings, to_np, cols)
 
 pytestmark = pytest.mark.gpu
 
@@ -204,7 +205,8 @@ def test_config4_bf16x6_trajectory_sampled_models():
     """The split-precision workload at full size (200x120x100x80, rank 12,
     1 % noise, 200 leave-one-out models, C = 2400) in the six-product split:
     4 sampled models compared with the oracle after each of 3 sweeps, every
-    result's error printed, gate 1e-5 (kappa(H) checked <= 1e4)."""
+    result's error printed, gate 1e-5 (kappa(H) checked <= 1e4); the tilings
+    bench.py times."""
     wl = _config4()
     models = [0, 66, 133, 199]
     sweeps = 3
@@ -213,6 +215,7 @@ def test_config4_bf16x6_trajectory_sampled_models():
                         models=models, record_factors=range(1, sweeps + 1))
     say("c4 bf16x6 trajectory: GPU")
     ctx = make_ctx(wl, precision=jk.JKC_SPLIT_BF16X6)
+    say("tilings", apply_tilings(ctx, shipped_tilings(wl, jk.JKC_SPLIT_BF16X6)))
     worst = 0.0
     for t in range(1, sweeps + 1):
         ctx.sweep(1)
@@ -226,13 +229,15 @@ def test_config4_bf16x6_trajectory_sampled_models():
 def test_config4_full_size_sampled_models(prec):
     """The split-precision workload at full size: 200x120x100x80 float64
     tensor of rank 12 with 1 % noise, 200 leave-one-out models of rank 12
-    (C = 2400); sampled models' MTTKRP in every mode at the init, normwise
+    (C = 2400), in the tilings bench.py times; sampled models' MTTKRP in
+every mode at the init, normwise
     and elementwise errors printed, gate 1e-5 (met by both splits here: at
     the init the sums do not cancel enough to reach the three-product
     floor)."""
     wl = _config4()
     say("c4 full split mttkrp", prec)
     ctx = make_ctx(wl, precision=prec)
+    say("tilings", apply_tilings(ctx, shipped_tilings(wl, prec)))   # precision 1 / 2
     worst = 0.0
     for n in range(4):
         M = to_np(ctx.mttkrp(n))
