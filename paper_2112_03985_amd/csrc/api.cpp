@@ -880,6 +880,7 @@ jkc_status enqueue_update(jkc_ctx* ctx, int n, double tol, int check_conv) {
   a.tol = tol;
   a.check_conv = check_conv;
   a.rmax = ctx->rmax;
+  a.uniform_rank = (ctx->uniform_rank > 0 && ctx->h_off == ctx->h_off_canon) ? ctx->uniform_rank : 0;
   if (ctx->update_kernel == 2)
     JKC_HIP(launch_update_rows(a, ctx->stream));
   else
@@ -1180,6 +1181,9 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
     goff += (int64_t)c.h_rank[k] * c.h_rank[k];
   }
   c.h_off_canon = c.h_off;
+  c.uniform_rank = c.h_rank.empty() ? 0 : c.h_rank[0];
+  for (int k = 1; k < pl.K; ++k)
+    if (c.h_rank[k] != c.uniform_rank) c.uniform_rank = 0;
   c.C_act = pl.C;
   // most expensive models first (rank^2 work per row), stable by index
   c.h_order.resize(pl.K);

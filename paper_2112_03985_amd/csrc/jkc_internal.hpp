@@ -147,6 +147,8 @@ struct UpdateArgs {
   double tol;                     // convergence tolerance (<= 0: off)
   int32_t check_conv;             // 1: update convergence flags
   int32_t rmax;                   // largest rank (LDS sizing)
+  int32_t uniform_rank;           // > 0: every model has this rank, model k at column k*R and
+                                  // Gram offset k*R*R (canonical layout; LDS-staged kernel)
   int64_t lds_doubles;            // > 0: LDS-staged kernel with this much dynamic LDS
   double* scratch;                // row-parallel update: per (model, chunk) sums
   double* Utmp;                   // row-parallel update: [In][ldc] unnormalised U
@@ -355,6 +357,7 @@ struct jkc_ctx {
   int32_t C_act = 0;
   bool compaction = true;
   std::vector<int32_t> h_off_canon;   // offsets of the canonical layout
+  int32_t uniform_rank = 0;           // the rank of every model when all are equal, else 0
   std::vector<int32_t> h_colmap;      // last relayout map, [C]
   int32_t* d_colmap = nullptr;        // [ldc]
   int update_kernel = 0;         // 0 LDS-staged, 1 global, 2 row-parallel

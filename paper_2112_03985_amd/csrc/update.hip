@@ -444,23 +444,40 @@ __global__ void __launch_bounds__(kUpdThreads) k_update_lds(const UpdateArgs a) 
   const int t = threadIdx.x;
   const int64_t plane = (int64_t)a.In * a.ldc;
 
-  for (int idx = blockIdx.x; idx < a.mt.K; idx += gridDim.x) {
+  // launch_update never gives this kernel more blocks than models, so every
+  // block has a first model: no bounds check (and no wait for the model
+  // count) before its loads are issued
+  int idx = blockIdx.x;
+  do {
     // one model per block when the grid covers them all (the cost order only
     // matters for a persistent grid): saves a dependent load
     const int k = (int)gridDim.x >= a.mt.K ? idx : a.mt.order[idx];
-    // every per-model scalar in one round of loads: the frozen check comes
-    // after them, so the table lookups do not wait for the status
+    // every per-model scalar in one round of loads; with one rank for every
+    // model in the canonical column layout the model's columns and Gram
+    // blocks follow from k, so the loads of H and M need no table lookup and
+    // go out with the status in a single round
     const int32_t st = a.status[k];
-    const int R = a.mt.rank[k];
-    const int off = a.mt.off[k];
-    const int64_t goff = a.mt.goff[k];
+    int R, off;
+    int64_t goff;
+    if (a.uniform_rank > 0) {
+      R = a.uniform_rank;
+      off = k * R;
+      goff = (int64_t)k * R * R;
+    } else {
+      R = a.mt.rank[k];
+      off = a.mt.off[k];
+      goff = a.mt.goff[k];
+    }
     // per-model scalars of the error step, fetched now (by every thread, with
     // no branch: a branch would make the compiler wait for them here) so that
     // their latency overlaps the update
     const double pre_nt2 = a.normT2[k];
     const double pre_fprev = a.fit_prev[k];
     const int32_t pre_it = a.iters[k];
-    if (st & (JKC_ST_CONVERGED | JKC_ST_NONFINITE)) continue;  // frozen (block-uniform)
+    // a frozen model (converged or non-finite) is skipped once H and M are
+    // staged (block-uniform; the loads are in bounds and nothing is written
+    // to global memory before the check), so the status wait overlaps them
+    const bool frozen = (st & (JKC_ST_CONVERGED | JKC_ST_NONFINITE)) != 0;
     const bool zero = a.n == a.nhat;
     const int RR = R * R;
 
@@ -483,7 +500,11 @@ __global__ void __launch_bounds__(kUpdThreads) k_update_lds(const UpdateArgs a) 
 #pragma unroll
         for (int mm = 0; mm < kMaxOrder; ++mm) {
           const bool use = mm < a.N && mm != a.n;
-          const double g = a.G[use ? mm : present][ge];
+          // the plane by selects between the four pointers (an index into
+          // the argument array would re-read the kernel arguments at a
+          // computed offset, one more dependent round before the loads)
+          const double* gp = mm == 0 ? a.G[0] : mm == 1 ? a.G[1] : mm == 2 ? a.G[2] : a.G[3];
+          const double g = (use ? gp : (present ? a.G[1] : a.G[0]))[ge];
           hg[u][mm] = use ? g : 1.0;
         }
       }
@@ -570,6 +591,7 @@ __global__ void __launch_bounds__(kUpdThreads) k_update_lds(const UpdateArgs a) 
     }
     if (!early) form_h();
     __syncthreads();
+    if (frozen) continue;
 
     // R > 8: Cholesky and L^{-1} in wavefront 0, in LDS with its steps
     // ordered by wavefront-local syncs: pivots by lane 0, the column below
@@ -785,7 +807,7 @@ __global__ void __launch_bounds__(kUpdThreads) k_update_lds(const UpdateArgs a) 
       a.status[k] = nst;
     }
     __syncthreads();
-  }
+  } while ((idx += gridDim.x) < a.mt.K);
 }
 
 __global__ void __launch_bounds__(kThreads) k_gram(const GramArgs a) {
