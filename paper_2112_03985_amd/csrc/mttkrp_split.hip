@@ -439,6 +439,7 @@ const std::vector<MttkrpVariant>& mttkrp_split3_variants() {
       JKC_BF_VARIANT(2, 2, 2, 2, 3),   // 64 x 64
       JKC_BF_VARIANT(2, 4, 4, 2, 3),   // 128 x 128, 8 wavefronts
       JKC_BF_VARIANT(4, 2, 4, 2, 3),   // 256 x 64, 8 wavefronts
+      JKC_BF_VARIANT(1, 4, 8, 2, 3),   // 128 x 128 (a 120-row mode in one row tile)
   };
   return v;
 }
