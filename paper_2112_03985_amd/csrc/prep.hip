@@ -138,13 +138,27 @@ __global__ void k_split_factor_t(const double* U, int32_t rows, int32_t ldc, int
 __global__ void k_slice_partial(const void* T, int32_t t_f32, int64_t inner, int32_t I,
                                 int64_t outer, int32_t chunks, double* part) {
   const int chunk = blockIdx.x;
+  auto at = [&](int64_t e) -> double {
+    return t_f32 ? (double)static_cast<const float*>(T)[e] : static_cast<const double*>(T)[e];
+  };
   for (int p = threadIdx.x; p < I; p += blockDim.x) {
     double s = 0.0;
-    for (int64_t b = chunk; b < outer; b += chunks) {
+    int64_t b = chunk;
+    if (inner == 1) {
+      // the sampled mode is mode 0: four slabs' loads issued together,
+      // added in the same ascending order
+      for (; b + 3 * (int64_t)chunks < outer; b += 4 * (int64_t)chunks) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = at((int64_t)p + (int64_t)I * (b + u * (int64_t)chunks));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s += v[u] * v[u];
+      }
+    }
+    for (; b < outer; b += chunks) {
       const int64_t base = inner * ((int64_t)p + (int64_t)I * b);
       for (int64_t a = 0; a < inner; ++a) {
-        const double v = t_f32 ? (double)static_cast<const float*>(T)[base + a]
-                               : static_cast<const double*>(T)[base + a];
+        const double v = at(base + a);
         s += v * v;
       }
     }
@@ -152,22 +166,45 @@ __global__ void k_slice_partial(const void* T, int32_t t_f32, int64_t inner, int
   }
 }
 
-__global__ void k_slice_final(const double* part, int32_t chunks, int32_t I, double* s_out) {
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < I; p += gridDim.x * blockDim.x) {
+// One block per slice p: thread t holds the chunk partials t, t + blockDim,
+// ... (ascending), then a pairwise tree over the threads in a fixed order.
+constexpr int kSliceFinalThreads = 256;
+__global__ void __launch_bounds__(kSliceFinalThreads)
+k_slice_final(const double* part, int32_t chunks, int32_t I, double* s_out) {
+  __shared__ double red[kSliceFinalThreads];
+  const int t = threadIdx.x;
+  for (int p = blockIdx.x; p < I; p += gridDim.x) {
     double s = 0.0;
-    for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * I + p];
-    s_out[p] = s;
+    for (int c = t; c < chunks; c += kSliceFinalThreads) s += part[(int64_t)c * I + p];
+    red[t] = s;
+    __syncthreads();
+    for (int w = kSliceFinalThreads / 2; w > 0; w >>= 1) {
+      if (t < w) red[t] += red[t + w];
+      __syncthreads();
+    }
+    if (t == 0) s_out[p] = red[0];
+    __syncthreads();
   }
 }
 
 // ||T_{-P}||^2 = sum of s_i over the rows i not left out of the model,
 // ascending i (the full norm for a model that leaves out nothing).
+// A left-out row adds +0.0, which leaves the (non-negative) running sum
+// unchanged bit for bit, so the loads carry no branch and go out four at a
+// time.
 __global__ void k_model_norms(const double* s, int32_t I, const uint8_t* lomask, int32_t K,
                               double* normT2) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
     double t = 0.0;
-    for (int i = 0; i < I; ++i)
-      if (!lomask[(int64_t)i * K + k]) t += s[i];
+    int i = 0;
+    for (; i + 4 <= I; i += 4) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = lomask[(int64_t)(i + u) * K + k] ? 0.0 : s[i + u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) t += v[u];
+    }
+    for (; i < I; ++i) t += lomask[(int64_t)i * K + k] ? 0.0 : s[i];
     normT2[k] = t;
   }
 }
@@ -340,8 +377,9 @@ hipError_t launch_slice_norms(const void* T, int32_t t_f32, int64_t inner, int32
                      chunks, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_slice_final, dim3(grid_for(I)), dim3(256), 0, s, partial, chunks, I,
-                     s_out);
+  const int fblocks = I < 1 ? 1 : I < 4096 ? (int)I : 4096;
+  hipLaunchKernelGGL(k_slice_final, dim3(fblocks), dim3(kSliceFinalThreads), 0, s, partial, chunks,
+                     I, s_out);
   return hipGetLastError();
 }
 
