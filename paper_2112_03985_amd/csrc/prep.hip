@@ -69,32 +69,38 @@ __device__ inline double bf16_to_double(uint16_t h) {
 // index jl, zero for jl >= I_low; wrap w over the other modes, lowest
 // fastest), stored in K blocks of 32: element (i, k) at
 // ((k / 32) * I_n + i) * 32 + k % 32, so the 32-K slice of every row is
-// one contiguous run of I_n * 64 bytes.  One thread per element.
+// one contiguous run of I_n * 64 bytes.  One thread per element.  IT is the
+// type of the index arithmetic: 32-bit when every element index fits (the
+// multi-index of each element costs a few integer divisions, about five
+// times cheaper in 32 bits than in 64), 64-bit otherwise.
+template <typename IT>
 __global__ void k_split_unfold(const void* src, int32_t src_f32, int32_t N, int64_t d0,
                                int64_t d1, int64_t d2, int64_t d3, int32_t n, int32_t low,
                                int32_t ilp, int32_t nterm, uint16_t* planes) {
-  const int64_t dims[4] = {d0, d1, d2, d3};
-  int64_t stride[4];
-  int64_t P = 1;
+  const IT dims[4] = {(IT)d0, (IT)d1, (IT)d2, (IT)d3};
+  IT stride[4];
+  IT P = 1;
   for (int m = 0; m < 4; ++m) {
     stride[m] = P;
     if (m < N) P *= dims[m];
   }
-  const int64_t I = dims[n];
-  const int64_t wraps = P / (I * dims[low]);
-  const int64_t total = I * (int64_t)ilp * wraps;
+  const IT I = dims[n];
+  const IT ilpT = (IT)ilp;
+  const IT wraps = P / (I * dims[low]);
+  const int64_t total = (int64_t)I * ilp * (int64_t)wraps;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t kk = e & 31;
-    const int64_t q = e >> 5;
-    const int64_t kb = q / I;
-    const int64_t i = q - kb * I;
-    const int64_t k = kb * 32 + kk;
-    const int64_t w = k / ilp;
-    const int64_t jl = k - w * ilp;
+    const IT ee = (IT)e;
+    const IT kk = ee & 31;
+    const IT q = ee >> 5;
+    const IT kb = q / I;
+    const IT i = q - kb * I;
+    const IT k = kb * 32 + kk;
+    const IT w = k / ilpT;
+    const IT jl = k - w * ilpT;
     double x = 0.0;
     if (jl < dims[low]) {
-      int64_t rem = w, off = i * stride[n] + jl * stride[low];
+      IT rem = w, off = i * stride[n] + jl * stride[low];
       for (int m = 0; m < N; ++m) {
         if (m == n || m == low) continue;
         off += (rem % dims[m]) * stride[m];
@@ -357,9 +363,15 @@ hipError_t launch_split_unfold(const void* src, int32_t src_f32, int32_t N, cons
   int64_t P = 1;
   for (int m = 0; m < N; ++m) P *= dims[m];
   const int64_t total = dims[n] * (int64_t)ilp * (P / (dims[n] * dims[low]));
-  hipLaunchKernelGGL(k_split_unfold, dim3(grid_for(total)), dim3(256), 0, s, src, src_f32, N,
-                     dims[0], N > 1 ? dims[1] : 1, N > 2 ? dims[2] : 1, N > 3 ? dims[3] : 1, n,
-                     low, ilp, nterm, planes);
+  // every element index (and every tensor offset, < P <= total) below 2^31
+  if (total < (int64_t(1) << 31))
+    hipLaunchKernelGGL(k_split_unfold<uint32_t>, dim3(grid_for(total)), dim3(256), 0, s, src,
+                       src_f32, N, dims[0], N > 1 ? dims[1] : 1, N > 2 ? dims[2] : 1,
+                       N > 3 ? dims[3] : 1, n, low, ilp, nterm, planes);
+  else
+    hipLaunchKernelGGL(k_split_unfold<int64_t>, dim3(grid_for(total)), dim3(256), 0, s, src,
+                       src_f32, N, dims[0], N > 1 ? dims[1] : 1, N > 2 ? dims[2] : 1,
+                       N > 3 ? dims[3] : 1, n, low, ilp, nterm, planes);
   return hipGetLastError();
 }
 
