@@ -171,6 +171,34 @@ def test_fit_with_tolerance_freezes_models():
         assert abs(fit[k] - res[k].fit_hist[-1]) <= 1e-6
 
 
+def test_uniform_rank_fast_path_matches_table_path():
+    """Models of one rank in the canonical column layout take the update's
+    fast path (columns and Gram blocks computed from the model index); once
+    convergence compaction has moved columns, the same models are updated
+    through the model table.  A tolerance fit with compaction must equal one
+    without it bit for bit, so both paths compute the same update."""
+    wl = synth.random_problem(41, (30, 25, 20), [4] * 12, [-1] + list(range(11)), noise=0.0,
+                              true_rank=4)
+    say("uniform-rank fast path vs table path")
+    a = make_ctx(wl)
+    b = make_ctx(wl)
+    b.set_compaction(False)
+    ia, fa, sa = a.fit(300, 1e-7)
+    ib, fb, sb = b.fit(300, 1e-7)
+    it = np.sort(np.asarray(ia))
+    say("iterations", it.tolist())
+    # at least 3 models (12 of 48 columns, past the one-fifth threshold)
+    # converged while others were still fitted: compaction moved columns
+    assert it[2] < it[-1]
+    assert np.array_equal(np.asarray(ia), np.asarray(ib))
+    assert np.array_equal(np.asarray(sa), np.asarray(sb))
+    assert np.array_equal(np.asarray(fa), np.asarray(fb))
+    for n in range(3):
+        ua, la = (to_np(x) for x in a.get_factors(n))
+        ub, lb = (to_np(x) for x in b.get_factors(n))
+        assert np.array_equal(ua, ub) and np.array_equal(la, lb)
+
+
 def test_remove_slice_bit_exact():
     import torch
     rng = np.random.default_rng(3)
