@@ -119,6 +119,8 @@ def shipped_tilings(wl, precision=0):
                                                "x".join(str(d) for d in wl.dims), ldc)
     out = {}
     for line in open(path):
+        if not line.strip():
+            continue
         k, geo, sp = line.strip().split("|")
         if not k.startswith(key):
             continue
