@@ -57,3 +57,30 @@ def test_bench_prints_one_json_line():
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in roof, k
     assert 0 < roof["frac"] < 1 and roof["peak"] == 78.6
+
+
+def test_shipped_tuning_table_covers_every_benchmark_workload():
+    """The tuned tilings bench.py times, and the full-size tests force, exist
+    for every workload: each mode, plus W for 3-way float64 problems.  The
+    shapes are those of the synthetic workloads (100x200x200 with 100 rank-5
+    models; 300x250x200 with ranks 1..10 x 5 inits x 300 samples; the 4-way
+    200x120x100x80 with 200 rank-12 models in both splits; 100x150x150
+    float32 with 100 rank-10 models)."""
+    from types import SimpleNamespace
+
+    import numpy as np
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from gpu_util import shipped_tilings
+
+    def wl(dims, C, dtype=np.float64):
+        return SimpleNamespace(dims=dims, ranks=np.array([C]), T=np.empty(0, dtype))
+
+    cases = [(wl((100, 200, 200), 500), 0, 4), (wl((300, 250, 200), 82500), 0, 4),
+             (wl((100, 150, 150), 1000, np.float32), 0, 4),
+             (wl((200, 120, 100, 80), 2400), 1, 4), (wl((200, 120, 100, 80), 2400), 2, 4)]
+    for w, precision, slots in cases:
+        t = shipped_tilings(w, precision)
+        assert sorted(t) == list(range(slots)), (w.dims, precision, sorted(t))
+        for geo, splits in t.values():
+            assert len(geo) == 6 and splits >= 1
