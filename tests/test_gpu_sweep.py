@@ -57,6 +57,28 @@ def test_sweeps_match_oracle(seed, dims, ranks, lo, nh):
         _compare_iteration(wl, ctx, res, t)
 
 
+@pytest.mark.parametrize("seed,dims,ranks,lo,true_rank", [
+    (32, (14, 12, 10), [1, 1, 1, 1], [-1, 0, 5, 13], 1),     # one rank 1 for every model
+    (33, (18, 15, 13), [9, 9, 9], [-1, 4, 17], 9),           # one rank above 8
+])
+def test_uniform_rank_sweeps_match_oracle(seed, dims, ranks, lo, true_rank):
+    """Models that all share one rank take the update's fast path (columns
+    and Gram blocks from the model index); rank 1 and a rank above 8 (the
+    factorisation in LDS after M is staged) against the oracle per
+    iteration."""
+    wl = synth.random_problem(seed, dims, ranks, lo, noise=0.1, true_rank=true_rank)
+    sweeps = 4
+    say("uniform-rank sweep parity", seed, ranks[0])
+    res = oracle.jk_als(np.asarray(wl.T), 0, wl.ranks, wl.left_out, wl.init, sweeps,
+                        record_factors=range(1, sweeps + 1))
+    for k in res:
+        assert np.linalg.cond(res[k].H_last) <= 1e4, k
+    ctx = make_ctx(wl)
+    for t in range(1, sweeps + 1):
+        ctx.sweep(1)
+        _compare_iteration(wl, ctx, res, t)
+
+
 def test_config1_trajectory_50_sweeps():
     """Config 1 (20x30x40, rank 3, 1 % noise, 20 leave-one-out + full
     model, 50 sweeps): every iteration of every model."""
