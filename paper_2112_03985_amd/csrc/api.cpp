@@ -943,6 +943,7 @@ jkc_status enqueue_gram(jkc_ctx* ctx, int n) {
   g.ldc = ctx->ldc;
   g.U = ctx->U[n];
   g.G = ctx->G[n];
+  g.uniform_rank = (ctx->uniform_rank > 0 && ctx->h_off == ctx->h_off_canon) ? ctx->uniform_rank : 0;
   JKC_HIP(launch_gram(g, ctx->stream));
   return JKC_OK;
 }
@@ -976,6 +977,7 @@ jkc_status enqueue_grad_assemble(jkc_ctx* ctx, double* loss) {
     g.normT2 = ctx->normT2;
     g.loss = loss;
     g.last_mode = (loss != nullptr && n == ctx->N - 1) ? 1 : 0;
+    g.uniform_rank = (ctx->uniform_rank > 0 && ctx->h_off == ctx->h_off_canon) ? ctx->uniform_rank : 0;
     JKC_HIP(launch_grad_assemble(g, ctx->stream));
   }
   return JKC_OK;
@@ -1055,6 +1057,7 @@ jkc_status enqueue_loss_grad(jkc_ctx* ctx, double* loss) {
     g.normT2 = ctx->normT2;
     g.loss = loss;
     g.last_mode = (loss != nullptr && n == ctx->N - 1) ? 1 : 0;
+    g.uniform_rank = (ctx->uniform_rank > 0 && ctx->h_off == ctx->h_off_canon) ? ctx->uniform_rank : 0;
     JKC_HIP(launch_grad_assemble(g, ctx->stream));
   }
   return JKC_OK;

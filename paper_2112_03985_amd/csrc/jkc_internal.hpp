@@ -191,6 +191,7 @@ struct GramArgs {
   int32_t ldc;
   const double* U;   // [rows][ldc]
   double* G;         // Gram plane
+  int32_t uniform_rank;   // > 0: every model has this rank, canonical layout (see UpdateArgs)
 };
 hipError_t launch_gram(const GramArgs& a, hipStream_t s);
 
@@ -281,6 +282,7 @@ struct GradArgs {
   const double* normT2;    // [K]
   double* loss;            // [K] (written when last_mode)
   int32_t last_mode;
+  int32_t uniform_rank;    // > 0: every model has this rank, canonical layout (see UpdateArgs)
 };
 hipError_t launch_grad_assemble(const GradArgs& a, hipStream_t s);
 hipError_t launch_scale_cols_by_model(const ModelTable& mt, const double* w,

@@ -810,10 +810,73 @@ __global__ void __launch_bounds__(kUpdThreads) k_update_lds(const UpdateArgs a) 
   } while ((idx += gridDim.x) < a.mt.K);
 }
 
-__global__ void __launch_bounds__(kThreads) k_gram(const GramArgs a) {
+// Gram blocks of the models' columns of U.  A model's rows x R block is
+// staged in LDS first, every load of it issued in one round (gram_block reads
+// global memory again for each of the R(R+1)/2 pairs, one dependent round
+// per pair and wavefront), then the pairs are formed from LDS with the same
+// per-lane order and wavefront sums as gram_block, so the bits are the same.
+// Blocks larger than the staging buffer use gram_block itself.
+constexpr int kGramStage = 6144;   // doubles (48 KB)
+constexpr int kGramThreads = 512;  // eight wavefronts share the R(R+1)/2 pairs
+__global__ void __launch_bounds__(kGramThreads) k_gram(const GramArgs a) {
+  __shared__ double Bs[kGramStage];
+  const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63;
+  constexpr int nw = kGramThreads / 64;
   for (int idx = blockIdx.x; idx < a.mt.K; idx += gridDim.x) {
-    const int k = a.mt.order[idx];
-    gram_block(a.U, a.rows, a.ldc, a.mt.off[k], a.mt.rank[k], a.G + a.mt.goff[k], nullptr);
+    // models are independent here: with a block per model no cost order is
+    // needed, and one rank in the canonical layout gives the offsets from k
+    // (no dependent table round before the loads of U)
+    const int k = (int)gridDim.x >= a.mt.K ? idx : a.mt.order[idx];
+    int R, off;
+    int64_t goff;
+    if (a.uniform_rank > 0) {
+      R = a.uniform_rank;
+      off = k * R;
+      goff = (int64_t)k * R * R;
+    } else {
+      R = a.mt.rank[k];
+      off = a.mt.off[k];
+      goff = a.mt.goff[k];
+    }
+    double* G = a.G + goff;
+    if ((int64_t)a.rows * R > kGramStage) {
+      gram_block(a.U, a.rows, a.ldc, off, R, G, nullptr);
+    } else {
+      const int n = a.rows * R;
+      for (int e0 = 0; e0 < n; e0 += 8 * kGramThreads) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + u * kGramThreads + t;
+          const int ec = e < n ? e : 0;
+          const int i = ec / R, r = ec - (ec / R) * R;
+          v[u] = a.U[(int64_t)i * a.ldc + off + r];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + u * kGramThreads + t;
+          if (e < n) Bs[e] = v[u];
+        }
+      }
+      __syncthreads();
+      const int npairs = R * (R + 1) / 2;
+      for (int pr = wave; pr < npairs; pr += nw) {
+        int r = 0, rem = pr;
+        while (rem >= R - r) {
+          rem -= R - r;
+          ++r;
+        }
+        const int c = r + rem;
+        double acc = 0.0;
+        for (int i = lane; i < a.rows; i += 64) acc += Bs[i * R + r] * Bs[i * R + c];
+        acc = wave_sum(acc);
+        if (lane == 0) {
+          G[r * R + c] = acc;
+          G[c * R + r] = acc;
+        }
+      }
+    }
     __syncthreads();
   }
 }
@@ -1029,22 +1092,65 @@ int persistent_grid(int K) {
 // grad = U H - M with H = *_{m != n} G_m; the left-out rows of the sampled
 // mode are 0.  After the last mode the loss
 // 1/2 (||T_{-P}||^2 + sum(H*G) - 2 sum(U*M)).
-__global__ void __launch_bounds__(kThreads) k_grad(const GradArgs a) {
+// The model's rows x R blocks of U and M are staged in LDS when they fit
+// (their loads in flight while H is formed), so each element's row of U is
+// read from LDS rather than with one dependent global round per element; the
+// element-to-thread assignment and every sum keep their order, so the bits
+// are those of the unstaged path.
+constexpr int kGradStage = 3072;   // doubles per block (U and M: 48 KB)
+constexpr int kGradThreads = 512;
+__global__ void __launch_bounds__(kGradThreads) k_grad(const GradArgs a) {
   __shared__ double H[kMaxRank][kLd];
-  __shared__ double s_red[kThreads];
+  __shared__ double s_red[kGradThreads / 64];
+  __shared__ double Us[kGradStage], Ms[kGradStage];
+  const int t = threadIdx.x;
   for (int idx = blockIdx.x; idx < a.mt.K; idx += gridDim.x) {
-    const int k = a.mt.order[idx];
-    const int R = a.mt.rank[k];
-    const int off = a.mt.off[k];
-    const int64_t goff = a.mt.goff[k];
-    build_h(a.Gp[0], a.Gp[1], a.Gp[2], a.Gp[3], a.N, a.n, goff, R, H);
+    const int k = (int)gridDim.x >= a.mt.K ? idx : a.mt.order[idx];
+    int R, off;
+    int64_t goff;
+    if (a.uniform_rank > 0) {
+      R = a.uniform_rank;
+      off = k * R;
+      goff = (int64_t)k * R * R;
+    } else {
+      R = a.mt.rank[k];
+      off = a.mt.off[k];
+      goff = a.mt.goff[k];
+    }
+    const int nel = a.In * R;
+    const bool staged = nel <= kGradStage;
+    if (staged) {
+      for (int e0 = 0; e0 < nel; e0 += 4 * kGradThreads) {
+        double vu[4], vm[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = e0 + u * kGradThreads + t;
+          const int ec = e < nel ? e : 0;
+          const int i = ec / R, r = ec - (ec / R) * R;
+          const int64_t at = (int64_t)i * a.ldc + off + r;
+          vu[u] = a.U[at];
+          vm[u] = a.Mfull[at];
+        }
+        if (e0 == 0) build_h(a.Gp[0], a.Gp[1], a.Gp[2], a.Gp[3], a.N, a.n, goff, R, H);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = e0 + u * kGradThreads + t;
+          if (e < nel) {
+            Us[e] = vu[u];
+            Ms[e] = vm[u];
+          }
+        }
+      }
+    } else {
+      build_h(a.Gp[0], a.Gp[1], a.Gp[2], a.Gp[3], a.N, a.n, goff, R, H);
+    }
     __syncthreads();
     double inner = 0.0;
-    for (int e = threadIdx.x; e < a.In * R; e += blockDim.x) {
+    for (int e = t; e < nel; e += blockDim.x) {
       const int i = e / R, r = e % R;
-      const double* urow = a.U + (int64_t)i * a.ldc + off;
+      const double* urow = staged ? Us + i * R : a.U + (int64_t)i * a.ldc + off;
       double g = 0.0;
-      const double m = a.Mfull[(int64_t)i * a.ldc + off + r];
+      const double m = staged ? Ms[e] : a.Mfull[(int64_t)i * a.ldc + off + r];
       if (!(a.n == a.nhat && left_out_row(a.mt, i, k))) {
         double uh = 0.0;
         for (int q = 0; q < R; ++q) uh += urow[q] * H[q][r];
@@ -1186,12 +1292,12 @@ hipError_t launch_update_rows(const UpdateArgs& a, hipStream_t s) {
 
 hipError_t launch_gram(const GramArgs& a, hipStream_t s) {
   if (a.mt.K <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gram, dim3(persistent_grid(a.mt.K)), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(k_gram, dim3(persistent_grid(a.mt.K)), dim3(kGramThreads), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_grad_assemble(const GradArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_grad, dim3(persistent_grid(a.mt.K)), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(k_grad, dim3(persistent_grid(a.mt.K)), dim3(kGradThreads), 0, s, a);
   return hipGetLastError();
 }
 
