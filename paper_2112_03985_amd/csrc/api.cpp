@@ -936,17 +936,23 @@ jkc_status enqueue_sweeps(jkc_ctx* ctx, int nsweeps, double tol, int check_conv)
   return JKC_OK;
 }
 
-jkc_status enqueue_gram(jkc_ctx* ctx, int n) {
+// Gram blocks of modes [n0, n1) in one launch.
+jkc_status enqueue_grams(jkc_ctx* ctx, int n0, int n1) {
   GramArgs g{};
   g.mt = ctx->table();
-  g.rows = (int32_t)ctx->dims[n];
   g.ldc = ctx->ldc;
-  g.U = ctx->U[n];
-  g.G = ctx->G[n];
+  g.nmodes = n1 - n0;
+  for (int q = 0; q < g.nmodes; ++q) {
+    g.rows[q] = (int32_t)ctx->dims[n0 + q];
+    g.U[q] = ctx->U[n0 + q];
+    g.G[q] = ctx->G[n0 + q];
+  }
   g.uniform_rank = (ctx->uniform_rank > 0 && ctx->h_off == ctx->h_off_canon) ? ctx->uniform_rank : 0;
   JKC_HIP(launch_gram(g, ctx->stream));
   return JKC_OK;
 }
+
+jkc_status enqueue_gram(jkc_ctx* ctx, int n) { return enqueue_grams(ctx, n, n + 1); }
 
 jkc_status enqueue_fold_lambda(jkc_ctx* ctx) {
   if (ctx->lambda_is_one) return JKC_OK;
@@ -1287,7 +1293,7 @@ jkc_status jk_cals_init(const jkc_problem* prob, const void* tensor, const doubl
     JKC_HIP(launch_pack_factor(init[n], pl.C, (int32_t)pl.dims[n], pl.C, pl.ldc, c.left_out(),
                                n == pl.nhat ? 1 : 0, c.U[n], st));
   }
-  for (int n = 0; n < pl.N; ++n) JKC_TRY(enqueue_gram(&c, n));
+  JKC_TRY(enqueue_grams(&c, 0, pl.N));
   JKC_HIP(launch_fill(c.lambda, pl.ldc, 1.0, st));
   JKC_HIP(launch_fill(c.err, pl.K, 0.0, st));
   JKC_HIP(launch_fill(c.fit, pl.K, 0.0, st));
@@ -1626,12 +1632,14 @@ jkc_status jk_cals_refine(jkc_ctx* ctx, int32_t steps, double* loss) {
   JKC_TRY(enqueue_fold_lambda(ctx));
   const double* G[kMaxOrder] = {ctx->G[0], ctx->G[1], ctx->G[2], ctx->G[3]};
   JKC_HIP(launch_gd_eta(ctx->table(), ctx->N, G, ctx->eta, ctx->stream));
+  // every mode's step in one launch (the gradients are all taken at the same
+  // point), then every mode's Gram blocks in one launch
+  const double* grads[kMaxOrder] = {ctx->grad[0], ctx->grad[1], ctx->grad[2], ctx->grad[3]};
   for (int s = 0; s < steps; ++s) {
     JKC_TRY(enqueue_loss_grad(ctx, nullptr));
-    for (int n = 0; n < ctx->N; ++n)
-      JKC_HIP(launch_gd_step(ctx->table(), ctx->eta, ctx->d_colmodel, ctx->U[n], ctx->grad[n],
-                             (int32_t)ctx->dims[n], ctx->ldc, ctx->C, ctx->stream));
-    for (int n = 0; n < ctx->N; ++n) JKC_TRY(enqueue_gram(ctx, n));
+    JKC_HIP(launch_gd_step(ctx->eta, ctx->d_colmodel, ctx->N, ctx->U, grads, ctx->dims, ctx->ldc,
+                           ctx->C, ctx->stream));
+    JKC_TRY(enqueue_grams(ctx, 0, ctx->N));
   }
   if (loss) JKC_TRY(enqueue_loss_grad(ctx, loss));
   g_last_error.clear();

@@ -185,12 +185,14 @@ hipError_t launch_update_rows(const UpdateArgs& a, hipStream_t s);
 int64_t update_lds_doubles(int rmax, int rows);
 hipError_t launch_update(const UpdateArgs& a, hipStream_t s);
 
+// Gram blocks of one or more modes in one launch (grid y: the modes).
 struct GramArgs {
   ModelTable mt;
-  int32_t rows;
   int32_t ldc;
-  const double* U;   // [rows][ldc]
-  double* G;         // Gram plane
+  int32_t nmodes;                    // modes in this launch (1..N)
+  int32_t rows[kMaxOrder];           // per launched mode
+  const double* U[kMaxOrder];        // [rows][ldc] factor per launched mode
+  double* G[kMaxOrder];              // its Gram plane
   int32_t uniform_rank;   // > 0: every model has this rank, canonical layout (see UpdateArgs)
 };
 hipError_t launch_gram(const GramArgs& a, hipStream_t s);
@@ -293,10 +295,11 @@ hipError_t launch_fold_lambda(double* U, int32_t rows, int32_t ldc, int32_t C,
                               double* lambda, hipStream_t s);
 hipError_t launch_gd_eta(const ModelTable& mt, int32_t N, const double* const* G,
                          double* eta, hipStream_t s);
-hipError_t launch_gd_step(const ModelTable& mt, const double* eta,
-                          const int32_t* colmodel, double* U,
-                          const double* grad, int32_t rows, int32_t ldc,
-                          int32_t C, hipStream_t s);
+// One gradient step U_n -= eta_k * grad_n for every mode n < N in one
+// launch (grid y: the mode).
+hipError_t launch_gd_step(const double* eta, const int32_t* colmodel, int32_t N,
+                          double* const* U, const double* const* grad,
+                          const int64_t* rows, int32_t ldc, int32_t C, hipStream_t s);
 
 }  // namespace jkc
 

@@ -823,6 +823,12 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(const GramArgs a) {
   const int t = threadIdx.x;
   const int wave = t >> 6, lane = t & 63;
   constexpr int nw = kGramThreads / 64;
+  // the launched mode of this block row (pointers by selects: an index into
+  // the argument arrays would re-read the kernel arguments)
+  const int mi = blockIdx.y;
+  const int rows = mi == 0 ? a.rows[0] : mi == 1 ? a.rows[1] : mi == 2 ? a.rows[2] : a.rows[3];
+  const double* Um = mi == 0 ? a.U[0] : mi == 1 ? a.U[1] : mi == 2 ? a.U[2] : a.U[3];
+  double* Gm = mi == 0 ? a.G[0] : mi == 1 ? a.G[1] : mi == 2 ? a.G[2] : a.G[3];
   for (int idx = blockIdx.x; idx < a.mt.K; idx += gridDim.x) {
     // models are independent here: with a block per model no cost order is
     // needed, and one rank in the canonical layout gives the offsets from k
@@ -839,11 +845,11 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(const GramArgs a) {
       off = a.mt.off[k];
       goff = a.mt.goff[k];
     }
-    double* G = a.G + goff;
-    if ((int64_t)a.rows * R > kGramStage) {
-      gram_block(a.U, a.rows, a.ldc, off, R, G, nullptr);
+    double* G = Gm + goff;
+    if ((int64_t)rows * R > kGramStage) {
+      gram_block(Um, rows, a.ldc, off, R, G, nullptr);
     } else {
-      const int n = a.rows * R;
+      const int n = rows * R;
       for (int e0 = 0; e0 < n; e0 += 8 * kGramThreads) {
         double v[8];
 #pragma unroll
@@ -851,7 +857,7 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(const GramArgs a) {
           const int e = e0 + u * kGramThreads + t;
           const int ec = e < n ? e : 0;
           const int i = ec / R, r = ec - (ec / R) * R;
-          v[u] = a.U[(int64_t)i * a.ldc + off + r];
+          v[u] = Um[(int64_t)i * a.ldc + off + r];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -869,7 +875,7 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(const GramArgs a) {
         }
         const int c = r + rem;
         double acc = 0.0;
-        for (int i = lane; i < a.rows; i += 64) acc += Bs[i * R + r] * Bs[i * R + c];
+        for (int i = lane; i < rows; i += 64) acc += Bs[i * R + r] * Bs[i * R + c];
         acc = wave_sum(acc);
         if (lane == 0) {
           G[r * R + c] = acc;
@@ -1227,9 +1233,16 @@ __global__ void k_gd_eta(const ModelTable mt, int32_t N, const double* G0, const
   }
 }
 
-__global__ void k_gd_step(const double* eta, const int32_t* colmodel, double* U,
-                          const double* grad, int32_t rows, int32_t ldc, int32_t C) {
-  const int64_t n = (int64_t)rows * C;
+__global__ void k_gd_step(const double* eta, const int32_t* colmodel, double* U0, double* U1,
+                          double* U2, double* U3, const double* g0, const double* g1,
+                          const double* g2, const double* g3, int64_t r0, int64_t r1, int64_t r2,
+                          int64_t r3, int32_t ldc, int32_t C) {
+  // this block row's mode (grid y)
+  const int mi = blockIdx.y;
+  double* U = mi == 0 ? U0 : mi == 1 ? U1 : mi == 2 ? U2 : U3;
+  const double* grad = mi == 0 ? g0 : mi == 1 ? g1 : mi == 2 ? g2 : g3;
+  const int64_t rows = mi == 0 ? r0 : mi == 1 ? r1 : mi == 2 ? r2 : r3;
+  const int64_t n = rows * C;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = e / C;
@@ -1292,7 +1305,8 @@ hipError_t launch_update_rows(const UpdateArgs& a, hipStream_t s) {
 
 hipError_t launch_gram(const GramArgs& a, hipStream_t s) {
   if (a.mt.K <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gram, dim3(persistent_grid(a.mt.K)), dim3(kGramThreads), 0, s, a);
+  if (a.nmodes < 1 || a.nmodes > kMaxOrder) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gram, dim3(persistent_grid(a.mt.K), a.nmodes), dim3(kGramThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1326,12 +1340,18 @@ hipError_t launch_gd_eta(const ModelTable& mt, int32_t N, const double* const* G
   return hipGetLastError();
 }
 
-hipError_t launch_gd_step(const ModelTable& mt, const double* eta, const int32_t* colmodel,
-                          double* U, const double* grad, int32_t rows, int32_t ldc, int32_t C,
-                          hipStream_t s) {
-  (void)mt;
-  hipLaunchKernelGGL(k_gd_step, dim3(grid_for((int64_t)rows * C)), dim3(256), 0, s, eta,
-                     colmodel, U, grad, rows, ldc, C);
+hipError_t launch_gd_step(const double* eta, const int32_t* colmodel, int32_t N,
+                          double* const* U, const double* const* grad, const int64_t* rows,
+                          int32_t ldc, int32_t C, hipStream_t s) {
+  if (N < 1 || N > kMaxOrder) return hipErrorInvalidValue;
+  int64_t rmax = 0;
+  for (int n = 0; n < N; ++n) rmax = std::max(rmax, rows[n]);
+  // modes past N repeat mode 0's pointers (their block rows are not launched)
+  auto at = [&](auto* p, int n) { return n < N ? p[n] : p[0]; };
+  hipLaunchKernelGGL(k_gd_step, dim3(grid_for(rmax * C), N), dim3(256), 0, s, eta, colmodel,
+                     at(U, 0), at(U, 1), at(U, 2), at(U, 3), at(grad, 0), at(grad, 1), at(grad, 2),
+                     at(grad, 3), rows[0], N > 1 ? rows[1] : 0, N > 2 ? rows[2] : 0,
+                     N > 3 ? rows[3] : 0, ldc, C);
   return hipGetLastError();
 }
 
