@@ -793,16 +793,16 @@ jkc_status enqueue_tree_w(jkc_ctx* ctx) {
   return JKC_OK;
 }
 
-// M_n for n = 0 or 1 from W into Mbuf (rows of the left-out samples are
-// cleared by the update, as for the fused kernel).
-jkc_status enqueue_tree_pass(jkc_ctx* ctx, int n) {
+// M_n for n = 0 or 1 from W into out ([I_n][ldc]; rows of the left-out
+// samples are cleared by the consumer, as for the fused kernel).
+jkc_status enqueue_tree_pass(jkc_ctx* ctx, int n, double* out) {
   const int64_t I0 = ctx->dims[0], I1 = ctx->dims[1];
   if (n == 0)   // M_0(i, c) = sum_j W(i + I_0 j, c) U_1(j, c)
     JKC_HIP(launch_tree_pass(ctx->Wtree, ctx->U[1], (int32_t)I1, 1, I0, (int32_t)I0, ctx->ldc,
-                             ctx->C_act, ctx->Mbuf, ctx->stream));
+                             ctx->C_act, out, ctx->stream));
   else          // M_1(j, c) = sum_i W(i + I_0 j, c) U_0(i, c)
     JKC_HIP(launch_tree_pass(ctx->Wtree, ctx->U[0], (int32_t)I0, I0, 1, (int32_t)I1, ctx->ldc,
-                             ctx->C_act, ctx->Mbuf, ctx->stream));
+                             ctx->C_act, out, ctx->stream));
   return JKC_OK;
 }
 
@@ -819,7 +819,7 @@ jkc_status enqueue_update(jkc_ctx* ctx, int n, double tol, int check_conv) {
   UpdateArgs a{};
   if (tree) {
     if (n == 0) JKC_TRY(enqueue_tree_w(ctx));
-    JKC_TRY(enqueue_tree_pass(ctx, n));
+    JKC_TRY(enqueue_tree_pass(ctx, n, ctx->Mbuf));
     a.partial = ctx->Mbuf;
     a.splits = 1;
     if (ctx->update_kernel == 2) {
@@ -965,27 +965,27 @@ jkc_status enqueue_fold_lambda(jkc_ctx* ctx) {
 }
 
 // All-mode gradient at the current factors (lambda folded), loss optional.
-// Loss and gradient assembly of every mode from the MTTKRPs held in
-// ctx->grad[n] (in place: the gradient overwrites its MTTKRP).
+// Loss and gradient assembly of every mode, in one launch, from the MTTKRPs
+// held in ctx->grad[n] (in place: the gradient overwrites its MTTKRP).
 jkc_status enqueue_grad_assemble(jkc_ctx* ctx, double* loss) {
-  for (int n = 0; n < ctx->N; ++n) {
-    GradArgs g{};
-    g.mt = ctx->table();
-    g.N = ctx->N;
-    g.n = n;
-    g.nhat = ctx->nhat;
-    g.In = (int32_t)ctx->dims[n];
-    g.ldc = ctx->ldc;
-    g.Mfull = ctx->grad[n];
-    g.U = ctx->U[n];
-    for (int m = 0; m < kMaxOrder; ++m) g.Gp[m] = ctx->G[m];
-    g.grad = ctx->grad[n];
-    g.normT2 = ctx->normT2;
-    g.loss = loss;
-    g.last_mode = (loss != nullptr && n == ctx->N - 1) ? 1 : 0;
-    g.uniform_rank = (ctx->uniform_rank > 0 && ctx->h_off == ctx->h_off_canon) ? ctx->uniform_rank : 0;
-    JKC_HIP(launch_grad_assemble(g, ctx->stream));
+  GradArgs g{};
+  g.mt = ctx->table();
+  g.N = ctx->N;
+  g.nhat = ctx->nhat;
+  g.n0 = 0;
+  g.nmodes = ctx->N;
+  g.ldc = ctx->ldc;
+  for (int m = 0; m < kMaxOrder; ++m) {
+    g.In[m] = m < ctx->N ? (int32_t)ctx->dims[m] : 0;
+    g.Mfull[m] = m < ctx->N ? ctx->grad[m] : nullptr;
+    g.U[m] = m < ctx->N ? ctx->U[m] : nullptr;
+    g.Gp[m] = ctx->G[m];
+    g.grad[m] = m < ctx->N ? ctx->grad[m] : nullptr;
   }
+  g.normT2 = ctx->normT2;
+  g.loss = loss;
+  g.uniform_rank = (ctx->uniform_rank > 0 && ctx->h_off == ctx->h_off_canon) ? ctx->uniform_rank : 0;
+  JKC_HIP(launch_grad_assemble(g, ctx->stream));
   return JKC_OK;
 }
 
@@ -1038,35 +1038,21 @@ jkc_status enqueue_loss_grad(jkc_ctx* ctx, double* loss) {
   const bool tree = ctx->use_tree;
   if (tree) JKC_TRY(enqueue_tree_w(ctx));
   ctx->tree_fresh = false;
+  // each mode's MTTKRP into its own gradient buffer, then one assembly launch
   for (int n = 0; n < ctx->N; ++n) {
     const bool from_w = tree && n < 2;
+    double* Mn = ctx->grad[n];
     if (from_w)
-      JKC_TRY(enqueue_tree_pass(ctx, n));
+      JKC_TRY(enqueue_tree_pass(ctx, n, Mn));
     else
-      JKC_TRY(enqueue_mttkrp_reduced(ctx, n, ctx->Mbuf, ctx->ldc, ctx->ldc));
-    if ((from_w || !reduced_clears_rows(ctx, n, ctx->tiling[n], ctx->Mbuf)) && n == ctx->nhat) {
+      JKC_TRY(enqueue_mttkrp_reduced(ctx, n, Mn, ctx->ldc, ctx->ldc));
+    if ((from_w || !reduced_clears_rows(ctx, n, ctx->tiling[n], Mn)) && n == ctx->nhat) {
       // the direct product still carries row p: clear it through a reduce pass
-      JKC_HIP(launch_reduce(ctx->Mbuf, 1, (int32_t)ctx->dims[n], ctx->ldc, ctx->ldc, ctx->left_out(),
-                            1, ctx->Mbuf, ctx->ldc, ctx->stream, nullptr));
+      JKC_HIP(launch_reduce(Mn, 1, (int32_t)ctx->dims[n], ctx->ldc, ctx->ldc, ctx->left_out(), 1,
+                            Mn, ctx->ldc, ctx->stream, nullptr));
     }
-    GradArgs g{};
-    g.mt = ctx->table();
-    g.N = ctx->N;
-    g.n = n;
-    g.nhat = ctx->nhat;
-    g.In = (int32_t)ctx->dims[n];
-    g.ldc = ctx->ldc;
-    g.Mfull = ctx->Mbuf;
-    g.U = ctx->U[n];
-    for (int m = 0; m < kMaxOrder; ++m) g.Gp[m] = ctx->G[m];
-    g.grad = ctx->grad[n];
-    g.normT2 = ctx->normT2;
-    g.loss = loss;
-    g.last_mode = (loss != nullptr && n == ctx->N - 1) ? 1 : 0;
-    g.uniform_rank = (ctx->uniform_rank > 0 && ctx->h_off == ctx->h_off_canon) ? ctx->uniform_rank : 0;
-    JKC_HIP(launch_grad_assemble(g, ctx->stream));
   }
-  return JKC_OK;
+  return enqueue_grad_assemble(ctx, loss);
 }
 
 // ---------------------------------------------------------------------------

@@ -273,17 +273,20 @@ int allmode_row_tiles(int I0);
 bool allmode_has_kernel(int nt, int bk);
 hipError_t launch_allmode(const AllModeArgs& a, hipStream_t s);
 
+// Gradient assembly of modes n0 .. n0 + nmodes - 1 in one launch (grid y:
+// the mode, n = n0 + blockIdx.y); entry q of the per-mode arrays belongs to
+// mode n0 + q.  Mfull[q] may equal grad[q] (assembled in place).
 struct GradArgs {
   ModelTable mt;
-  int32_t N, n, nhat;
-  int32_t In, ldc;
-  const double* Mfull;     // [In][ldc] reduced MTTKRP of mode n (row-p zeroed)
-  const double* U;         // [In][ldc] factor of mode n
-  const double* Gp[kMaxOrder];   // Gram planes
-  double* grad;            // [In][ldc] gradient of mode n (out)
+  int32_t N, nhat;
+  int32_t n0, nmodes, ldc;
+  int32_t In[kMaxOrder];
+  const double* Mfull[kMaxOrder];  // [In][ldc] MTTKRP of the mode
+  const double* U[kMaxOrder];      // [In][ldc] factor of the mode
+  const double* Gp[kMaxOrder];     // Gram planes of every mode
+  double* grad[kMaxOrder];         // [In][ldc] gradient of the mode (out)
   const double* normT2;    // [K]
-  double* loss;            // [K] (written when last_mode)
-  int32_t last_mode;
+  double* loss;            // [K]: written by the blocks of mode N - 1 when not null
   int32_t uniform_rank;    // > 0: every model has this rank, canonical layout (see UpdateArgs)
 };
 hipError_t launch_grad_assemble(const GradArgs& a, hipStream_t s);

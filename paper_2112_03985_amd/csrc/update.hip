@@ -1094,9 +1094,10 @@ int persistent_grid(int K) {
   return K < 1024 ? K : 1024;
 }
 
-// Gradient of the CP loss for one mode (all-at-once CP), per model:
+// Gradient of the CP loss (all-at-once CP) per model and mode, every mode
+// of the launch at once (grid y: the mode):
 // grad = U H - M with H = *_{m != n} G_m; the left-out rows of the sampled
-// mode are 0.  After the last mode the loss
+// mode are 0.  The blocks of the last mode also give the loss
 // 1/2 (||T_{-P}||^2 + sum(H*G) - 2 sum(U*M)).
 // The model's rows x R blocks of U and M are staged in LDS when they fit
 // (their loads in flight while H is formed), so each element's row of U is
@@ -1110,6 +1111,15 @@ __global__ void __launch_bounds__(kGradThreads) k_grad(const GradArgs a) {
   __shared__ double s_red[kGradThreads / 64];
   __shared__ double Us[kGradStage], Ms[kGradStage];
   const int t = threadIdx.x;
+  // this block row's mode, its arrays chosen by selects (no dynamic index
+  // into the argument block)
+  const int mq = blockIdx.y;
+  const int n = a.n0 + mq;
+  const int In = mq == 0 ? a.In[0] : mq == 1 ? a.In[1] : mq == 2 ? a.In[2] : a.In[3];
+  const double* Mq = mq == 0 ? a.Mfull[0] : mq == 1 ? a.Mfull[1] : mq == 2 ? a.Mfull[2] : a.Mfull[3];
+  const double* Uq = mq == 0 ? a.U[0] : mq == 1 ? a.U[1] : mq == 2 ? a.U[2] : a.U[3];
+  double* gq = mq == 0 ? a.grad[0] : mq == 1 ? a.grad[1] : mq == 2 ? a.grad[2] : a.grad[3];
+  const bool last_mode = a.loss != nullptr && n == a.N - 1;
   for (int idx = blockIdx.x; idx < a.mt.K; idx += gridDim.x) {
     const int k = (int)gridDim.x >= a.mt.K ? idx : a.mt.order[idx];
     int R, off;
@@ -1123,7 +1133,7 @@ __global__ void __launch_bounds__(kGradThreads) k_grad(const GradArgs a) {
       off = a.mt.off[k];
       goff = a.mt.goff[k];
     }
-    const int nel = a.In * R;
+    const int nel = In * R;
     const bool staged = nel <= kGradStage;
     if (staged) {
       for (int e0 = 0; e0 < nel; e0 += 4 * kGradThreads) {
@@ -1134,10 +1144,10 @@ __global__ void __launch_bounds__(kGradThreads) k_grad(const GradArgs a) {
           const int ec = e < nel ? e : 0;
           const int i = ec / R, r = ec - (ec / R) * R;
           const int64_t at = (int64_t)i * a.ldc + off + r;
-          vu[u] = a.U[at];
-          vm[u] = a.Mfull[at];
+          vu[u] = Uq[at];
+          vm[u] = Mq[at];
         }
-        if (e0 == 0) build_h(a.Gp[0], a.Gp[1], a.Gp[2], a.Gp[3], a.N, a.n, goff, R, H);
+        if (e0 == 0) build_h(a.Gp[0], a.Gp[1], a.Gp[2], a.Gp[3], a.N, n, goff, R, H);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int e = e0 + u * kGradThreads + t;
@@ -1148,27 +1158,27 @@ __global__ void __launch_bounds__(kGradThreads) k_grad(const GradArgs a) {
         }
       }
     } else {
-      build_h(a.Gp[0], a.Gp[1], a.Gp[2], a.Gp[3], a.N, a.n, goff, R, H);
+      build_h(a.Gp[0], a.Gp[1], a.Gp[2], a.Gp[3], a.N, n, goff, R, H);
     }
     __syncthreads();
     double inner = 0.0;
     for (int e = t; e < nel; e += blockDim.x) {
       const int i = e / R, r = e % R;
-      const double* urow = staged ? Us + i * R : a.U + (int64_t)i * a.ldc + off;
+      const double* urow = staged ? Us + i * R : Uq + (int64_t)i * a.ldc + off;
       double g = 0.0;
-      const double m = staged ? Ms[e] : a.Mfull[(int64_t)i * a.ldc + off + r];
-      if (!(a.n == a.nhat && left_out_row(a.mt, i, k))) {
+      const double m = staged ? Ms[e] : Mq[(int64_t)i * a.ldc + off + r];
+      if (!(n == a.nhat && left_out_row(a.mt, i, k))) {
         double uh = 0.0;
         for (int q = 0; q < R; ++q) uh += urow[q] * H[q][r];
         g = uh - m;
       }
-      a.grad[(int64_t)i * a.ldc + off + r] = g;
+      gq[(int64_t)i * a.ldc + off + r] = g;
       inner += urow[r] * m;
     }
     const double in_all = block_sum(inner, s_red);
-    if (a.last_mode && threadIdx.x == 0) {
+    if (last_mode && threadIdx.x == 0) {
       const double in = in_all;
-      const double* Gn = (a.n == 0 ? a.Gp[0] : a.n == 1 ? a.Gp[1] : a.n == 2 ? a.Gp[2] : a.Gp[3]) + goff;
+      const double* Gn = (n == 0 ? a.Gp[0] : n == 1 ? a.Gp[1] : n == 2 ? a.Gp[2] : a.Gp[3]) + goff;
       double quad = 0.0;
       for (int r = 0; r < R; ++r)
         for (int s = 0; s < R; ++s) quad += H[r][s] * Gn[r * R + s];
@@ -1311,7 +1321,9 @@ hipError_t launch_gram(const GramArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_grad_assemble(const GradArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_grad, dim3(persistent_grid(a.mt.K)), dim3(kGradThreads), 0, s, a);
+  if (a.nmodes < 1 || a.nmodes > kMaxOrder) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_grad, dim3(persistent_grid(a.mt.K), a.nmodes), dim3(kGradThreads), 0, s,
+                     a);
   return hipGetLastError();
 }
 
