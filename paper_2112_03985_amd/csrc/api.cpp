@@ -937,7 +937,9 @@ jkc_status enqueue_sweeps(jkc_ctx* ctx, int nsweeps, double tol, int check_conv)
 }
 
 // Gram blocks of modes [n0, n1) in one launch.
-jkc_status enqueue_grams(jkc_ctx* ctx, int n0, int n1) {
+// Gram blocks of modes n0 .. n1-1 in one launch; with eta, each mode's
+// factor first takes the gradient step U_n -= eta_k grad_n (same launch).
+jkc_status enqueue_grams(jkc_ctx* ctx, int n0, int n1, const double* eta = nullptr) {
   GramArgs g{};
   g.mt = ctx->table();
   g.ldc = ctx->ldc;
@@ -946,7 +948,9 @@ jkc_status enqueue_grams(jkc_ctx* ctx, int n0, int n1) {
     g.rows[q] = (int32_t)ctx->dims[n0 + q];
     g.U[q] = ctx->U[n0 + q];
     g.G[q] = ctx->G[n0 + q];
+    g.grad[q] = ctx->grad[n0 + q];
   }
+  g.eta = eta;
   g.uniform_rank = (ctx->uniform_rank > 0 && ctx->h_off == ctx->h_off_canon) ? ctx->uniform_rank : 0;
   JKC_HIP(launch_gram(g, ctx->stream));
   return JKC_OK;
@@ -1038,19 +1042,16 @@ jkc_status enqueue_loss_grad(jkc_ctx* ctx, double* loss) {
   const bool tree = ctx->use_tree;
   if (tree) JKC_TRY(enqueue_tree_w(ctx));
   ctx->tree_fresh = false;
-  // each mode's MTTKRP into its own gradient buffer, then one assembly launch
+  // each mode's MTTKRP into its own gradient buffer, then one assembly launch.
+  // A pass from W leaves the left-out rows of the sampled mode as computed:
+  // the assembly writes 0 there and those factor rows are 0, so they add
+  // nothing to the loss (as in the one-pass all-mode path).
   for (int n = 0; n < ctx->N; ++n) {
-    const bool from_w = tree && n < 2;
     double* Mn = ctx->grad[n];
-    if (from_w)
+    if (tree && n < 2)
       JKC_TRY(enqueue_tree_pass(ctx, n, Mn));
     else
       JKC_TRY(enqueue_mttkrp_reduced(ctx, n, Mn, ctx->ldc, ctx->ldc));
-    if ((from_w || !reduced_clears_rows(ctx, n, ctx->tiling[n], Mn)) && n == ctx->nhat) {
-      // the direct product still carries row p: clear it through a reduce pass
-      JKC_HIP(launch_reduce(Mn, 1, (int32_t)ctx->dims[n], ctx->ldc, ctx->ldc, ctx->left_out(), 1,
-                            Mn, ctx->ldc, ctx->stream, nullptr));
-    }
   }
   return enqueue_grad_assemble(ctx, loss);
 }
@@ -1618,14 +1619,11 @@ jkc_status jk_cals_refine(jkc_ctx* ctx, int32_t steps, double* loss) {
   JKC_TRY(enqueue_fold_lambda(ctx));
   const double* G[kMaxOrder] = {ctx->G[0], ctx->G[1], ctx->G[2], ctx->G[3]};
   JKC_HIP(launch_gd_eta(ctx->table(), ctx->N, G, ctx->eta, ctx->stream));
-  // every mode's step in one launch (the gradients are all taken at the same
-  // point), then every mode's Gram blocks in one launch
-  const double* grads[kMaxOrder] = {ctx->grad[0], ctx->grad[1], ctx->grad[2], ctx->grad[3]};
+  // every mode's step and Gram blocks in one launch (the gradients are all
+  // taken at the same point)
   for (int s = 0; s < steps; ++s) {
     JKC_TRY(enqueue_loss_grad(ctx, nullptr));
-    JKC_HIP(launch_gd_step(ctx->eta, ctx->d_colmodel, ctx->N, ctx->U, grads, ctx->dims, ctx->ldc,
-                           ctx->C, ctx->stream));
-    JKC_TRY(enqueue_grams(ctx, 0, ctx->N));
+    JKC_TRY(enqueue_grams(ctx, 0, ctx->N, ctx->eta));
   }
   if (loss) JKC_TRY(enqueue_loss_grad(ctx, loss));
   g_last_error.clear();

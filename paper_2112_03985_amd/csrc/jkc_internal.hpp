@@ -191,9 +191,13 @@ struct GramArgs {
   int32_t ldc;
   int32_t nmodes;                    // modes in this launch (1..N)
   int32_t rows[kMaxOrder];           // per launched mode
-  const double* U[kMaxOrder];        // [rows][ldc] factor per launched mode
+  double* U[kMaxOrder];              // [rows][ldc] factor per launched mode
   double* G[kMaxOrder];              // its Gram plane
   int32_t uniform_rank;   // > 0: every model has this rank, canonical layout (see UpdateArgs)
+  // gradient step before the Gram blocks when eta is not null:
+  // U -= eta[k] * grad on model k's columns (grad [rows][ldc] per mode)
+  const double* eta;                 // [K]
+  const double* grad[kMaxOrder];
 };
 hipError_t launch_gram(const GramArgs& a, hipStream_t s);
 
@@ -298,11 +302,6 @@ hipError_t launch_fold_lambda(double* U, int32_t rows, int32_t ldc, int32_t C,
                               double* lambda, hipStream_t s);
 hipError_t launch_gd_eta(const ModelTable& mt, int32_t N, const double* const* G,
                          double* eta, hipStream_t s);
-// One gradient step U_n -= eta_k * grad_n for every mode n < N in one
-// launch (grid y: the mode).
-hipError_t launch_gd_step(const double* eta, const int32_t* colmodel, int32_t N,
-                          double* const* U, const double* const* grad,
-                          const int64_t* rows, int32_t ldc, int32_t C, hipStream_t s);
 
 }  // namespace jkc
 

@@ -815,7 +815,10 @@ __global__ void __launch_bounds__(kUpdThreads) k_update_lds(const UpdateArgs a) 
 // global memory again for each of the R(R+1)/2 pairs, one dependent round
 // per pair and wavefront), then the pairs are formed from LDS with the same
 // per-lane order and wavefront sums as gram_block, so the bits are the same.
-// Blocks larger than the staging buffer use gram_block itself.
+// Blocks larger than the staging buffer use gram_block itself.  With a
+// step (eta not null) each element of the block first becomes
+// U - eta_k grad, written back to U, and the Gram block is that of the
+// stepped factor: every mode's gradient step and Gram blocks in one launch.
 constexpr int kGramStage = 6144;   // doubles (48 KB)
 constexpr int kGramThreads = 512;  // eight wavefronts share the R(R+1)/2 pairs
 __global__ void __launch_bounds__(kGramThreads) k_gram(const GramArgs a) {
@@ -827,8 +830,11 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(const GramArgs a) {
   // the argument arrays would re-read the kernel arguments)
   const int mi = blockIdx.y;
   const int rows = mi == 0 ? a.rows[0] : mi == 1 ? a.rows[1] : mi == 2 ? a.rows[2] : a.rows[3];
-  const double* Um = mi == 0 ? a.U[0] : mi == 1 ? a.U[1] : mi == 2 ? a.U[2] : a.U[3];
+  double* Um = mi == 0 ? a.U[0] : mi == 1 ? a.U[1] : mi == 2 ? a.U[2] : a.U[3];
   double* Gm = mi == 0 ? a.G[0] : mi == 1 ? a.G[1] : mi == 2 ? a.G[2] : a.G[3];
+  const double* gm =
+      mi == 0 ? a.grad[0] : mi == 1 ? a.grad[1] : mi == 2 ? a.grad[2] : a.grad[3];
+  const bool step = a.eta != nullptr;
   for (int idx = blockIdx.x; idx < a.mt.K; idx += gridDim.x) {
     // models are independent here: with a block per model no cost order is
     // needed, and one rank in the canonical layout gives the offsets from k
@@ -847,9 +853,19 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(const GramArgs a) {
     }
     double* G = Gm + goff;
     if ((int64_t)rows * R > kGramStage) {
+      if (step) {
+        const double eta = a.eta[k];
+        for (int e = t; e < rows * R; e += kGramThreads) {
+          const int i = e / R, r = e - (e / R) * R;
+          const int64_t at = (int64_t)i * a.ldc + off + r;
+          Um[at] = Um[at] - eta * gm[at];
+        }
+        __syncthreads();   // the block's own writes, read back by gram_block
+      }
       gram_block(Um, rows, a.ldc, off, R, G, nullptr);
     } else {
       const int n = rows * R;
+      const double eta = step ? a.eta[k] : 0.0;
       for (int e0 = 0; e0 < n; e0 += 8 * kGramThreads) {
         double v[8];
 #pragma unroll
@@ -858,6 +874,25 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(const GramArgs a) {
           const int ec = e < n ? e : 0;
           const int i = ec / R, r = ec - (ec / R) * R;
           v[u] = Um[(int64_t)i * a.ldc + off + r];
+        }
+        if (step) {
+          double g[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kGramThreads + t;
+            const int ec = e < n ? e : 0;
+            const int i = ec / R, r = ec - (ec / R) * R;
+            g[u] = gm[(int64_t)i * a.ldc + off + r];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kGramThreads + t;
+            v[u] = v[u] - eta * g[u];
+            if (e < n) {
+              const int i = e / R, r = e - (e / R) * R;
+              Um[(int64_t)i * a.ldc + off + r] = v[u];
+            }
+          }
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -1243,25 +1278,6 @@ __global__ void k_gd_eta(const ModelTable mt, int32_t N, const double* G0, const
   }
 }
 
-__global__ void k_gd_step(const double* eta, const int32_t* colmodel, double* U0, double* U1,
-                          double* U2, double* U3, const double* g0, const double* g1,
-                          const double* g2, const double* g3, int64_t r0, int64_t r1, int64_t r2,
-                          int64_t r3, int32_t ldc, int32_t C) {
-  // this block row's mode (grid y)
-  const int mi = blockIdx.y;
-  double* U = mi == 0 ? U0 : mi == 1 ? U1 : mi == 2 ? U2 : U3;
-  const double* grad = mi == 0 ? g0 : mi == 1 ? g1 : mi == 2 ? g2 : g3;
-  const int64_t rows = mi == 0 ? r0 : mi == 1 ? r1 : mi == 2 ? r2 : r3;
-  const int64_t n = rows * C;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e / C;
-    const int c = (int)(e % C);
-    const int64_t at = i * ldc + c;
-    U[at] -= eta[colmodel[c]] * grad[at];
-  }
-}
-
 __global__ void k_count_active(const int32_t* status, int32_t K, int32_t* out) {
   __shared__ int s[256];
   int c = 0;
@@ -1349,21 +1365,6 @@ hipError_t launch_gd_eta(const ModelTable& mt, int32_t N, const double* const* G
                          hipStream_t s) {
   hipLaunchKernelGGL(k_gd_eta, dim3(grid_for(mt.K)), dim3(256), 0, s, mt, N, G[0], G[1],
                      N > 2 ? G[2] : nullptr, N > 3 ? G[3] : nullptr, eta);
-  return hipGetLastError();
-}
-
-hipError_t launch_gd_step(const double* eta, const int32_t* colmodel, int32_t N,
-                          double* const* U, const double* const* grad, const int64_t* rows,
-                          int32_t ldc, int32_t C, hipStream_t s) {
-  if (N < 1 || N > kMaxOrder) return hipErrorInvalidValue;
-  int64_t rmax = 0;
-  for (int n = 0; n < N; ++n) rmax = std::max(rmax, rows[n]);
-  // modes past N repeat mode 0's pointers (their block rows are not launched)
-  auto at = [&](auto* p, int n) { return n < N ? p[n] : p[0]; };
-  hipLaunchKernelGGL(k_gd_step, dim3(grid_for(rmax * C), N), dim3(256), 0, s, eta, colmodel,
-                     at(U, 0), at(U, 1), at(U, 2), at(U, 3), at(grad, 0), at(grad, 1), at(grad, 2),
-                     at(grad, 3), rows[0], N > 1 ? rows[1] : 0, N > 2 ? rows[2] : 0,
-                     N > 3 ? rows[3] : 0, ldc, C);
   return hipGetLastError();
 }
 
