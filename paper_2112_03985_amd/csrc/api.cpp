@@ -936,7 +936,6 @@ jkc_status enqueue_sweeps(jkc_ctx* ctx, int nsweeps, double tol, int check_conv)
   return JKC_OK;
 }
 
-// Gram blocks of modes [n0, n1) in one launch.
 // Gram blocks of modes n0 .. n1-1 in one launch; with eta, each mode's
 // factor first takes the gradient step U_n -= eta_k grad_n (same launch).
 jkc_status enqueue_grams(jkc_ctx* ctx, int n0, int n1, const double* eta = nullptr) {
